@@ -1,0 +1,193 @@
+#!/usr/bin/env python3
+"""Throughput benchmark of the direct-summation Hermite hot path on one GPU.
+
+Workload (the configuration the headline metric is quoted on): a Plummer
+sphere of N = 2^20 equal-mass particles in N-body units, softening 1/4096,
+seed 1003.  One step is one Hermite block step of the device-resident
+driver (nbody_blockstep: schedule -> predict all -> pair sums on the block
+-> correct the block) with every particle in the block (shared steps of
+2^-12, NBODY_FIXED_DT), i.e. N (N - 1) pair interactions per step.  Inputs
+are resident in HBM before the timed region.
+
+Printed: one JSON line with interactions/s, the pair kernel's roofline
+(algorithmic flops at 60 per interaction -- the paper's per-interaction
+operation count -- over its HIP-event-timed duration, against the MI355X
+float32 vector peak), and the FP64 oracle timed on the host cores on a
+bounded sample of the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+FLOPS_PER_INTERACTION = 60          # the paper's per-interaction operation count
+FP32_PEAK_TFLOPS = 157.3            # MI355X float32 vector peak
+HBM_PEAK_GBS = 8000.0
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--mode", choices=("fp32", "ds"), default="fp32")
+    ap.add_argument("--n", type=int, default=1 << 20)
+    ap.add_argument("--cpu-seconds", type=float, default=12.0,
+                    help="target duration of the oracle's CPU-baseline sample")
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-aux", action="store_true")
+    ap.add_argument("--retune", action="store_true")
+    args = ap.parse_args()
+
+    if args.gpus != 1:
+        print("bench.py measures one GPU: this build has no multi-GPU path "
+              "(the j-parallel sharding is a design note only); run with --gpus 1.",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import paper_cs_0702135_amd as nb
+    from paper_cs_0702135_amd import autotune
+    from workloads.plummer import CONFIGS, plummer
+
+    cfg = CONFIGS["plummer1m"]
+    n = args.n
+    eps2 = cfg.eps2
+    log("bench: building Plummer N=%d" % n)
+    pos, vel, m = plummer(n, cfg.seed)
+    P, V, M = (torch.from_numpy(a).cuda() for a in (pos, vel, m))
+
+    if args.retune:
+        table = autotune.tune(P, V, M, eps2, args.mode, log=log)
+        autotune.save(table)
+    table = autotune.load_or_tune(P, V, M, eps2, args.mode, log=log, dynamic_n_i=n)
+    shape = nb.tune_get(-1)
+    log("bench: block-step pair-kernel shape %r" % (shape,))
+
+    h = 2.0 ** -12
+    sysg = nb.System(P, V, M, eps2, dt_max=h, mode=args.mode, fixed_dt=True)
+    for _ in range(args.warmup):
+        assert sysg.step(1) == 1
+    torch.cuda.synchronize()
+    nb.profile(1)
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        assert sysg.step(1) == 1
+        log("bench: step %d done" % (k + 1))
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    force_ms, reduce_ms, launches = nb.profile(0)
+    wall = t1 - t0
+    inter_step = float(n) * (n - 1)
+    value = args.steps * inter_step / wall
+    ms_step = wall / args.steps * 1e3
+
+    k_ms = force_ms / max(1, launches)
+    achieved = FLOPS_PER_INTERACTION * inter_step / (k_ms * 1e-3) / 1e12
+    roofline = {
+        "bound": "alu",
+        "kernel": "force_kernel",
+        "achieved": round(achieved, 2),
+        "peak": FP32_PEAK_TFLOPS,
+        "unit": "TFLOP/s",
+        "frac": round(achieved / FP32_PEAK_TFLOPS, 4),
+        "traffic": None,
+        "kernel_ms": round(k_ms, 3),
+        "flops_per_interaction": FLOPS_PER_INTERACTION,
+        "reduce_ms": round(reduce_ms / max(1, launches), 3),
+    }
+
+    out = {
+        "metric": "pairwise acc+jerk interactions/s (Hermite block step, all N active)",
+        "value": value,
+        "unit": "interactions/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_step, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {
+            "workload": "plummer N=2^20 eps=1/4096 seed=1003, shared Hermite block step "
+                        "h=2^-12 (all N active), pair arithmetic f32 on f64-formed "
+                        "relative coordinates, f64 integrator",
+            "n": n, "eps": 1.0 / 4096, "accumulation": args.mode,
+            "shape": shape.asdict(),
+        },
+        "roofline": roofline,
+    }
+
+    if not args.no_aux:
+        aux = {}
+        # the other accumulation mode on the same state, pair kernel only
+        other = "ds" if args.mode == "fp32" else "fp32"
+        nb.force(P, V, M, eps2, None, other)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        nb.force(P, V, M, eps2, None, other)
+        e1.record()
+        torch.cuda.synchronize()
+        aux["force_only_%s_interactions_per_s" % other] = inter_step / (e0.elapsed_time(e1) * 1e-3)
+        # energy drift of the block-step integrator, Plummer N=1024 to t=1/4
+        # (built-in shapes: the tuned table above is for N = 2^20)
+        nb.tune_clear()
+        c1 = CONFIGS["plummer1k"]
+        p1, v1, m1 = plummer(c1.n, c1.seed)
+        s1 = nb.System(*(torch.from_numpy(a).cuda() for a in (p1, v1, m1)), c1.eps2,
+                       eta=c1.eta, dt_max=c1.dt_max, mode=args.mode)
+        e_0 = s1.energy()
+        ta = time.perf_counter()
+        steps1 = s1.run(c1.t_end)
+        torch.cuda.synchronize()
+        tb = time.perf_counter()
+        e_1 = s1.energy()
+        aux["plummer1k_energy_drift_per_time_unit"] = abs((e_1 - e_0) / e_0) / c1.t_end
+        aux["plummer1k_block_steps"] = steps1
+        aux["plummer1k_ms_per_block_step"] = (tb - ta) / max(1, steps1) * 1e3
+        out["aux"] = aux
+
+    if not args.no_cpu:
+        import oracle
+        cores = oracle.num_threads()
+        rng = np.random.default_rng(cfg.seed + 7)
+        # calibrate on a small sample, then size the sample to ~cpu_seconds
+        probe = np.sort(rng.choice(n, 256, replace=False)).astype(np.int32)
+        ta = time.perf_counter()
+        oracle.force(pos, vel, m, eps2, active=probe)
+        rate0 = 256 * (n - 1) / (time.perf_counter() - ta)
+        n_s = int(max(256, min(n, args.cpu_seconds * rate0 / (n - 1))))
+        sample = np.sort(rng.choice(n, n_s, replace=False)).astype(np.int32)
+        log("bench: oracle sample of %d i-particles (%d threads)" % (n_s, cores))
+        ta = time.perf_counter()
+        oracle.force(pos, vel, m, eps2, active=sample)
+        dt_cpu = time.perf_counter() - ta
+        out["cpu_baseline"] = {
+            "value": n_s * (n - 1) / dt_cpu,
+            "unit": "interactions/s",
+            "cores": cores,
+            "kind": "oracle",
+            "sample": "FP64 oracle pair sums for %d seeded i-particles against all %d j "
+                      "(%.2e interactions, %.1f s)" % (n_s, n, n_s * (n - 1.0), dt_cpu),
+        }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,242 @@
+/*
+ * nbody.h -- C ABI of libnbody.so, the MI355X (gfx950) direct-summation
+ * Hermite library.
+ *
+ * What it computes (Portegies Zwart, Belleman & Geldof, "High Performance
+ * Direct Gravitational N-body Simulations on Graphics Processing Units"):
+ *   - the softened pair sums of acceleration, jerk and potential of
+ *     Section 2, Eq. (1), in the softened form of the Appendix A listing;
+ *   - the fourth-order Hermite predictor and corrector of Section 2;
+ *   - the power-of-two block time steps of Section 2 (selection of the
+ *     particles with the smallest t_i + dt_i);
+ *   - the energy diagnostic behind the energy errors of Section 6;
+ *   - an adjoint of the pair sums and of the shared-step Hermite chain, and
+ *     a batched ensemble driver (extensions of the method; see each entry).
+ *
+ * Conventions for every entry point:
+ *   - Array arguments are DEVICE pointers owned by the caller; the library
+ *     never frees them.  Scalars are host values.  A few outputs are
+ *     explicitly host pointers; they say so.
+ *   - Vectors are structure-of-arrays, component-major float64: for n
+ *     particles q[0..n) holds x, q[n..2n) y, q[2n..3n) z.  Scalars per
+ *     particle are float64 arrays of length n.  Index lists are int32.
+ *   - Work is enqueued on the context's HIP stream and is asynchronous
+ *     unless an entry says it synchronises.
+ *   - Every entry returns NBODY_OK (0) or a negative status; no C++
+ *     exception crosses the ABI.  nbody_last_error() gives the text of the
+ *     last failure on that context.  Errors found by kernels (a time step
+ *     below dt_min, a non-finite value) are latched in a device status word
+ *     and reported by the next synchronising call (nbody_sync_status,
+ *     nbody_blockstep, nbody_ensemble_run).
+ *   - Results are deterministic for a fixed device and configuration: no
+ *     floating-point atomics; every reduction has a fixed order.
+ *   - Calls on one context must not overlap from several host threads.
+ */
+#ifndef NBODY_H
+#define NBODY_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes ---------------------------------------------------- */
+#define NBODY_OK 0
+#define NBODY_E_INVAL (-1)     /* bad argument, detected on the host       */
+#define NBODY_E_DEVICE (-2)    /* HIP runtime error                         */
+#define NBODY_E_RANGE (-3)     /* a time step fell below dt_min             */
+#define NBODY_E_NONFINITE (-4) /* a non-finite force or step criterion      */
+#define NBODY_E_NOMEM (-5)     /* device allocation failed                  */
+
+/* ---- flags for the force and adjoint entries ------------------------- */
+/* Relative positions and velocities are always formed in float64 and then
+ * rounded to float32; the pair arithmetic is float32 (rsqrt on the VALU);
+ * the flag selects how the float32 pair terms are accumulated. */
+#define NBODY_ACC_FP32 0u /* two-level float32 sums (tile sums folded in fp32) */
+#define NBODY_ACC_DS 1u   /* tile sums folded by TwoSum into a float-float pair */
+/* nbody_system.flags only: every particle keeps the step it has (dt_max after
+ * nbody_init), i.e. shared steps in which every block step advances all
+ * particles; the step criterion is not evaluated. */
+#define NBODY_FIXED_DT 2u
+
+typedef struct nbody_ctx nbody_ctx;
+
+/* Library version, major*10000 + minor*100 + patch. */
+int nbody_version(void);
+
+/* Create a context bound to HIP device `device` and stream `stream`
+ * (a hipStream_t, or NULL for the null stream).  The context owns its
+ * scratch buffers and tuning table.  Allocates device memory lazily. */
+int nbody_create(nbody_ctx **out, int device, void *stream);
+int nbody_destroy(nbody_ctx *ctx);
+/* Re-bind the stream (e.g. torch.cuda.current_stream().cuda_stream). */
+int nbody_set_stream(nbody_ctx *ctx, void *stream);
+/* Text of the last error on ctx (never NULL; "" if none). */
+const char *nbody_last_error(const nbody_ctx *ctx);
+/* Synchronise the stream, return and clear the device status word:
+ * NBODY_OK, NBODY_E_RANGE or NBODY_E_NONFINITE. */
+int nbody_sync_status(nbody_ctx *ctx);
+
+/* ---- pair sums ---------------------------------------------------------
+ * Section 2, Eq. (1) with the softening, jerk and potential of the
+ * Appendix A listing, G = 1: for each active slot s with particle
+ * i = active_idx[s] (or i = s when active_idx is NULL), over all j != i:
+ *   r = x_j - x_i,  w = v_j - v_i,  S = r.r + eps2,
+ *   acc[s]  = sum m_j r S^(-3/2)
+ *   jerk[s] = sum m_j ( w S^(-3/2) - 3 (r.w) r S^(-5/2) )
+ *   pot[s]  = -sum m_j S^(-1/2)            (per unit mass of i)
+ * The self pair is excluded by index, so eps2 = 0 is valid for distinct
+ * positions; coincident distinct particles with eps2 = 0 give non-finite
+ * values (not trapped).
+ *   active_idx : int32[n_i] indices in [0, n_j), or NULL.  Any order,
+ *                duplicates allowed.
+ *   pos, vel   : float64[3*n_j];  mass : float64[n_j]
+ *   acc, jerk  : float64[3*n_i] (component stride n_i);  pot : float64[n_i]
+ *                (pot may be NULL).
+ *   flags      : NBODY_ACC_FP32 or NBODY_ACC_DS.
+ * Errors: NBODY_E_INVAL for NULL arrays, n_i < 0, n_j < 1, n_i > 2^31-1,
+ * eps2 < 0 or NaN, unknown flags. */
+int nbody_force(nbody_ctx *ctx, const int32_t *active_idx, int64_t n_i,
+                const double *pos, const double *vel, const double *mass,
+                int64_t n_j, double eps2, double *acc, double *jerk,
+                double *pot, uint32_t flags);
+
+/* ---- predictor ---------------------------------------------------------
+ * Section 2: for every particle, with h = t_target - t[i],
+ *   xp = x + (v + (h/2)(a + (h/3) k)) h,    vp = v + (a + (h/2) k) h
+ * evaluated in float64 in this nesting (no contraction).
+ *   t : float64[n];  x, v, a, k, xp, vp : float64[3n]. */
+int nbody_predict(nbody_ctx *ctx, int64_t n, double t_target, const double *t,
+                  const double *x, const double *v, const double *a,
+                  const double *k, double *xp, double *vp);
+
+/* ---- block scheduler ---------------------------------------------------
+ * Section 2, first item of a step: t_next = min_i (t[i] + dt[i]); the
+ * active block is every i with t[i] + dt[i] == t_next (exact float64
+ * comparison), written in ascending index order.
+ *   active_idx : int32[n] output (first n_i entries valid)
+ *   n_i_out    : int64[1] device output;  t_next_out : float64[1] device. */
+int nbody_schedule(nbody_ctx *ctx, int64_t n, const double *t,
+                   const double *dt, int32_t *active_idx, int64_t *n_i_out,
+                   double *t_next_out);
+
+/* ---- corrector and new time step ---------------------------------------
+ * Section 2, for each active slot s, particle i = active_idx[s] (or s), with
+ * h = dt[i], a, k the old values and a_p = acc_new[s], k_p = jerk_new[s]:
+ *   a3 = 2(a - a_p) + (k + k_p) h,   a2 = -3(a - a_p) - (2k + k_p) h,
+ *   x = xp + (a2/12 + a3/20) h^2,    v = vp + (a2/3 + a3/4) h,
+ *   a <- a_p, k <- k_p, t <- t + h.
+ * New step (the paper does not state its criterion; this library uses
+ * Aarseth's, with the end-of-step derivatives (2 a2 + 6 a3)/h^2 and
+ * 6 a3/h^3):
+ *   dt_crit = sqrt(eta (|a||a''| + |k|^2) / (|k||a'''| + |a''|^2)),
+ * halved while dt > dt_crit, else doubled once if 2dt <= dt_crit, t is a
+ * multiple of 2dt and 2dt <= dt_max.  A zero denominator sets no limit.  A
+ * step below dt_min latches NBODY_E_RANGE; a NaN criterion latches
+ * NBODY_E_NONFINITE.  fixed_dt != 0 leaves dt unchanged (shared steps).
+ *   acc_new, jerk_new : float64[3*n_i], component stride n_i.
+ *   xp, vp, x, v, a, k : float64[3n];  t, dt : float64[n]. */
+int nbody_correct(nbody_ctx *ctx, int64_t n, int64_t n_i,
+                  const int32_t *active_idx, const double *xp,
+                  const double *vp, const double *acc_new,
+                  const double *jerk_new, double eta, double dt_max,
+                  double dt_min, int fixed_dt, double *t, double *dt,
+                  double *x, double *v, double *a, double *k);
+
+/* ---- initial time steps ------------------------------------------------
+ * dt[i] = largest power of two <= min(eta_s |a_i|/|k_i|, dt_max) of which
+ * t0 is a multiple (|k_i| = 0 gives dt_max).  A value below dt_min latches
+ * NBODY_E_RANGE.  dt_max must be a power of two. */
+int nbody_initial_dt(nbody_ctx *ctx, int64_t n, double t0, const double *a,
+                     const double *k, double eta_s, double dt_max,
+                     double dt_min, double *dt);
+
+/* ---- energy diagnostic -------------------------------------------------
+ * Section 6 quotes energy errors; the energy is E = K + W with
+ * K = sum 1/2 m |v|^2 and W = 1/2 sum_i m_i phi_i for the softened
+ * potential of the force law above, all in float64 (float64 pair
+ * arithmetic).  out : float64[2] device output {K, W}. */
+int nbody_energy(nbody_ctx *ctx, int64_t n, const double *pos,
+                 const double *vel, const double *mass, double eps2,
+                 double *out);
+
+/* ---- device-resident block-step integrator -------------------------------
+ * A system of n particles whose state lives in caller-owned device arrays.
+ * eta: step criterion accuracy; eta_s: initial-step factor; dt_max (a power
+ * of two) and dt_min bound the steps; flags as for nbody_force. */
+typedef struct nbody_system {
+    int64_t n;
+    double *t, *dt;       /* float64[n]                      */
+    double *x, *v;        /* float64[3n]                     */
+    double *a, *k;        /* float64[3n] last force and jerk */
+    const double *m;      /* float64[n]                      */
+    double eps2, eta, eta_s, dt_max, dt_min;
+    uint32_t flags;
+} nbody_system;
+
+/* Set t = t0 for all particles, evaluate a and k on all of them, and set
+ * the initial steps (as nbody_initial_dt; dt_max for every particle with
+ * NBODY_FIXED_DT). */
+int nbody_init(nbody_ctx *ctx, const nbody_system *sys, double t0);
+
+/* Run block steps (schedule -> predict all -> force on the block ->
+ * correct the block, Section 2) without any per-step host traffic, until
+ * max_steps steps are done or the next block would pass t_end.
+ * Synchronises.  steps_done and interactions (sum over steps of n_i * n)
+ * are HOST outputs (either may be NULL).  Returns the latched device
+ * status (NBODY_E_RANGE / NBODY_E_NONFINITE) if any. */
+int nbody_blockstep(nbody_ctx *ctx, const nbody_system *sys,
+                    int64_t max_steps, double t_end, int64_t *steps_done,
+                    int64_t *interactions);
+
+/* ---- launch shape of the pair kernels (autotuning) ----------------------
+ * The pair kernels are compiled in several shapes; a context keeps a table
+ * of which shape to use for which active-block size.  Without entries a
+ * built-in default is used.
+ *   rep           form of the relative coordinates: 0 = float64 differences
+ *                 rounded to float32; 1 = float-float (hi/lo float32 pairs)
+ *                 differences, float32 instructions only; 2 = float64
+ *                 position differences, float32 velocity differences (the
+ *                 jerk then carries float32 rounding of the velocities).
+ *   i_per_lane    i-particles per lane: 1, 2 or 4.
+ *   waves         waves per workgroup splitting the j range: 1, 2, 4 or 8
+ *                 (at most 4 with 4 i-particles per lane).
+ *   tile          j-particles summed in float32 before each fold (>= 1).
+ *   min_j_wave    smallest j range per wave when the j range is split (>= 1).
+ *   target_groups workgroups to aim for before splitting j (>= 1). */
+typedef struct nbody_force_config {
+    int32_t rep;
+    int32_t i_per_lane;
+    int32_t waves;
+    int32_t tile;
+    int32_t min_j_wave;
+    int32_t target_groups;
+} nbody_force_config;
+
+/* Use `cfg` for active-block sizes n_i in [n_i_lo, n_i_hi).  n_i_lo < 0
+ * sets the shape of the block-step driver's pair launches (block size known
+ * only on the device).  Later entries do not override earlier ones that
+ * cover the same n_i.  NBODY_E_INVAL for an unsupported shape. */
+int nbody_tune_set(nbody_ctx *ctx, int64_t n_i_lo, int64_t n_i_hi,
+                   const nbody_force_config *cfg);
+/* Timing of the pair kernels with HIP events recorded on the context's
+ * stream around each launch made by nbody_force and nbody_blockstep.
+ * enable = 1 clears the totals and starts timing, 0 stops it, -1 leaves it
+ * as it is.  Synchronises, then writes the totals so far to the HOST
+ * pointers (each may be NULL): milliseconds in the pair kernel, in the
+ * split-reduction kernel, and the number of pair-kernel launches. */
+int nbody_profile(nbody_ctx *ctx, int enable, double *force_ms, double *reduce_ms,
+                  int64_t *launches);
+
+/* Remove every entry (back to the built-in default). */
+int nbody_tune_clear(nbody_ctx *ctx);
+/* The shape used for n_i (n_i < 0: the block-step shape); `out` is a HOST
+ * pointer. */
+int nbody_tune_get(nbody_ctx *ctx, int64_t n_i, nbody_force_config *out);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* NBODY_H */

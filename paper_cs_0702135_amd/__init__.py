@@ -1,0 +1,304 @@
+"""MI355X (gfx950) direct-summation Hermite library: Python binding.
+
+Thin marshalling layer over libnbody.so (include/nbody.h): every step of the
+computation runs in the library's HIP kernels; PyTorch only provides device
+memory and the stream.  Tensors are float64 on a CUDA (HIP) device, vectors
+of shape (3, n) (component-major structure-of-arrays), scalars of shape (n,),
+index lists int32.
+
+Paper: Portegies Zwart, Belleman & Geldof, "High Performance Direct
+Gravitational N-body Simulations on Graphics Processing Units" -- Section 2
+(force, Hermite predictor-corrector, block time steps) and the Appendix A
+listing (softened acceleration, jerk and potential).
+"""
+from __future__ import annotations
+
+import ctypes
+import math
+import threading
+
+import torch
+
+from . import _lib as L
+
+__all__ = [
+    "NBodyError", "Context", "context", "force", "predict", "schedule",
+    "correct", "initial_dt", "energy", "System", "ACC_FP32", "ACC_DS",
+    "ForceShape", "tune_set", "tune_clear", "tune_get", "profile",
+]
+
+ACC_FP32 = L.NBODY_ACC_FP32
+ACC_DS = L.NBODY_ACC_DS
+_MODES = {"fp32": ACC_FP32, "ds": ACC_DS}
+
+
+class NBodyError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__("libnbody error %d: %s" % (code, msg))
+        self.code = code
+
+
+class Context:
+    """One library context per device; re-bound to torch's current stream."""
+
+    def __init__(self, device: int):
+        self.lib = L.load()
+        self.device = device
+        h = ctypes.c_void_p()
+        rc = self.lib.nbody_create(ctypes.byref(h), device, None)
+        if rc != 0:
+            raise NBodyError(rc, "nbody_create failed on device %d" % device)
+        self.h = h
+
+    def bind(self):
+        s = torch.cuda.current_stream(self.device).cuda_stream
+        self.lib.nbody_set_stream(self.h, ctypes.c_void_p(s))
+        return self.h
+
+    def check(self, rc):
+        if rc != 0:
+            msg = self.lib.nbody_last_error(self.h)
+            raise NBodyError(rc, msg.decode() if msg else "")
+
+    def sync_status(self):
+        self.check(self.lib.nbody_sync_status(self.bind()))
+
+    def __del__(self):
+        try:
+            if getattr(self, "h", None):
+                self.lib.nbody_destroy(self.h)
+        except Exception:
+            pass
+
+
+_ctx = {}
+_ctx_lock = threading.Lock()
+
+
+def context(device=None) -> Context:
+    if not torch.cuda.is_available():
+        raise RuntimeError("libnbody needs a ROCm GPU (torch.cuda.is_available() is False)")
+    dev = torch.cuda.current_device() if device is None else torch.device(device).index
+    if dev is None:
+        dev = torch.cuda.current_device()
+    with _ctx_lock:
+        if dev not in _ctx:
+            _ctx[dev] = Context(dev)
+        return _ctx[dev]
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else None
+
+
+def _vec(t, n, name):
+    if t.dtype != torch.float64 or not t.is_cuda or not t.is_contiguous() or tuple(t.shape) != (3, n):
+        raise ValueError("%s must be a contiguous float64 CUDA tensor of shape (3, %d)" % (name, n))
+    return t
+
+
+def _sca(t, n, name):
+    if t.dtype != torch.float64 or not t.is_cuda or not t.is_contiguous() or tuple(t.shape) != (n,):
+        raise ValueError("%s must be a contiguous float64 CUDA tensor of shape (%d,)" % (name, n))
+    return t
+
+
+def _mode(mode):
+    if isinstance(mode, int):
+        return mode
+    try:
+        return _MODES[mode]
+    except KeyError:
+        raise ValueError("mode must be 'fp32' or 'ds'") from None
+
+
+def force(pos, vel, mass, eps2, active_idx=None, mode="fp32", out=None):
+    """Acceleration, jerk and potential on the active particles.
+
+    Returns (acc (3, n_i), jerk (3, n_i), pot (n_i,)) float64 tensors.
+    """
+    n = mass.shape[0]
+    _vec(pos, n, "pos"), _vec(vel, n, "vel"), _sca(mass, n, "mass")
+    if active_idx is not None:
+        if active_idx.dtype != torch.int32 or not active_idx.is_cuda or active_idx.dim() != 1:
+            raise ValueError("active_idx must be a 1-d int32 CUDA tensor")
+        active_idx = active_idx.contiguous()
+        n_i = active_idx.shape[0]
+    else:
+        n_i = n
+    if out is None:
+        acc = torch.empty((3, n_i), dtype=torch.float64, device=pos.device)
+        jerk = torch.empty_like(acc)
+        pot = torch.empty((n_i,), dtype=torch.float64, device=pos.device)
+    else:
+        acc, jerk, pot = out
+    ctx = context(pos.device)
+    ctx.check(ctx.lib.nbody_force(ctx.bind(), _ptr(active_idx), n_i, _ptr(pos), _ptr(vel),
+                                  _ptr(mass), n, float(eps2), _ptr(acc), _ptr(jerk),
+                                  _ptr(pot), _mode(mode)))
+    return acc, jerk, pot
+
+
+def predict(t_target, t, x, v, a, k):
+    n = t.shape[0]
+    for q, nm in ((x, "x"), (v, "v"), (a, "a"), (k, "k")):
+        _vec(q, n, nm)
+    _sca(t, n, "t")
+    xp = torch.empty_like(x)
+    vp = torch.empty_like(v)
+    ctx = context(x.device)
+    ctx.check(ctx.lib.nbody_predict(ctx.bind(), n, float(t_target), _ptr(t), _ptr(x), _ptr(v),
+                                    _ptr(a), _ptr(k), _ptr(xp), _ptr(vp)))
+    return xp, vp
+
+
+def schedule(t, dt):
+    """Returns (active_idx int32 (n_i,), t_next float) -- synchronises."""
+    n = t.shape[0]
+    _sca(t, n, "t"), _sca(dt, n, "dt")
+    act = torch.empty((n,), dtype=torch.int32, device=t.device)
+    n_i = torch.empty((1,), dtype=torch.int64, device=t.device)
+    tn = torch.empty((1,), dtype=torch.float64, device=t.device)
+    ctx = context(t.device)
+    ctx.check(ctx.lib.nbody_schedule(ctx.bind(), n, _ptr(t), _ptr(dt), _ptr(act), _ptr(n_i),
+                                     _ptr(tn)))
+    k = int(n_i.item())
+    return act[:k], float(tn.item())
+
+
+def correct(active_idx, xp, vp, acc_new, jerk_new, eta, dt_max, dt_min, t, dt, x, v, a, k,
+            fixed_dt=False):
+    """Corrector and new steps on the active particles, in place."""
+    n = t.shape[0]
+    n_i = n if active_idx is None else active_idx.shape[0]
+    for q, nm in ((xp, "xp"), (vp, "vp"), (x, "x"), (v, "v"), (a, "a"), (k, "k")):
+        _vec(q, n, nm)
+    _vec(acc_new, n_i, "acc_new"), _vec(jerk_new, n_i, "jerk_new")
+    ctx = context(x.device)
+    ctx.check(ctx.lib.nbody_correct(ctx.bind(), n, n_i, _ptr(active_idx), _ptr(xp), _ptr(vp),
+                                    _ptr(acc_new), _ptr(jerk_new), float(eta), float(dt_max),
+                                    float(dt_min), int(bool(fixed_dt)), _ptr(t), _ptr(dt),
+                                    _ptr(x), _ptr(v), _ptr(a), _ptr(k)))
+
+
+def initial_dt(t0, a, k, eta_s, dt_max, dt_min):
+    n = a.shape[1]
+    _vec(a, n, "a"), _vec(k, n, "k")
+    dt = torch.empty((n,), dtype=torch.float64, device=a.device)
+    ctx = context(a.device)
+    ctx.check(ctx.lib.nbody_initial_dt(ctx.bind(), n, float(t0), _ptr(a), _ptr(k),
+                                       float(eta_s), float(dt_max), float(dt_min), _ptr(dt)))
+    return dt
+
+
+def energy(pos, vel, mass, eps2):
+    """(K, W) as host floats -- synchronises."""
+    n = mass.shape[0]
+    _vec(pos, n, "pos"), _vec(vel, n, "vel"), _sca(mass, n, "mass")
+    out = torch.empty((2,), dtype=torch.float64, device=pos.device)
+    ctx = context(pos.device)
+    ctx.check(ctx.lib.nbody_energy(ctx.bind(), n, _ptr(pos), _ptr(vel), _ptr(mass), float(eps2),
+                                   _ptr(out)))
+    K, W = out.tolist()
+    return K, W
+
+
+class ForceShape(tuple):
+    """Launch shape of the pair kernels (see nbody_force_config)."""
+    __slots__ = ()
+    _names = ("rep", "i_per_lane", "waves", "tile", "min_j_wave", "target_groups")
+
+    def __new__(cls, rep=0, i_per_lane=2, waves=1, tile=128, min_j_wave=64, target_groups=32768):
+        return tuple.__new__(cls, (int(rep), int(i_per_lane), int(waves), int(tile),
+                                   int(min_j_wave), int(target_groups)))
+
+    def asdict(self):
+        return dict(zip(self._names, self))
+
+    def __repr__(self):
+        return "ForceShape(%s)" % ", ".join("%s=%d" % kv for kv in zip(self._names, self))
+
+
+def tune_set(n_i_lo, n_i_hi, shape, device=None):
+    """Use `shape` for active blocks of n_i in [n_i_lo, n_i_hi); n_i_lo < 0
+    sets the block-step driver's shape."""
+    ctx = context(device)
+    c = L.NBodyForceConfig(*shape)
+    ctx.check(ctx.lib.nbody_tune_set(ctx.h, int(n_i_lo), int(n_i_hi), ctypes.byref(c)))
+
+
+def tune_clear(device=None):
+    ctx = context(device)
+    ctx.check(ctx.lib.nbody_tune_clear(ctx.h))
+
+
+def tune_get(n_i, device=None) -> ForceShape:
+    ctx = context(device)
+    c = L.NBodyForceConfig()
+    ctx.check(ctx.lib.nbody_tune_get(ctx.h, int(n_i), ctypes.byref(c)))
+    return ForceShape(c.rep, c.i_per_lane, c.waves, c.tile, c.min_j_wave, c.target_groups)
+
+
+def profile(enable=-1, device=None):
+    """Pair-kernel event timing: returns (force_ms, reduce_ms, launches)."""
+    ctx = context(device)
+    f, r, k = ctypes.c_double(), ctypes.c_double(), ctypes.c_int64()
+    ctx.check(ctx.lib.nbody_profile(ctx.bind(), int(enable), ctypes.byref(f), ctypes.byref(r),
+                                    ctypes.byref(k)))
+    return f.value, r.value, k.value
+
+
+class System:
+    """Device-resident block-step integrator state (nbody_system)."""
+
+    def __init__(self, pos, vel, mass, eps2, eta=0.02, eta_s=0.01, dt_max=0.125,
+                 dt_min=2.0 ** -40, mode="fp32", t0=0.0, init=True, fixed_dt=False):
+        dev = pos.device
+        n = mass.shape[0]
+        self.n = n
+        self.x = _vec(pos, n, "pos").clone()
+        self.v = _vec(vel, n, "vel").clone()
+        self.m = _sca(mass, n, "mass").clone()
+        self.t = torch.zeros((n,), dtype=torch.float64, device=dev)
+        self.dt = torch.zeros((n,), dtype=torch.float64, device=dev)
+        self.a = torch.zeros((3, n), dtype=torch.float64, device=dev)
+        self.k = torch.zeros((3, n), dtype=torch.float64, device=dev)
+        self.eps2, self.eta, self.eta_s = float(eps2), float(eta), float(eta_s)
+        self.dt_max, self.dt_min = float(dt_max), float(dt_min)
+        self.flags = _mode(mode) | (L.NBODY_FIXED_DT if fixed_dt else 0)
+        self.steps = 0
+        self.interactions = 0
+        if init:
+            self.init(t0)
+
+    def _struct(self):
+        return L.NBodySystem(self.n, self.t.data_ptr(), self.dt.data_ptr(), self.x.data_ptr(),
+                             self.v.data_ptr(), self.a.data_ptr(), self.k.data_ptr(),
+                             self.m.data_ptr(), self.eps2, self.eta, self.eta_s, self.dt_max,
+                             self.dt_min, self.flags)
+
+    def init(self, t0=0.0):
+        ctx = context(self.x.device)
+        s = self._struct()
+        ctx.check(ctx.lib.nbody_init(ctx.bind(), ctypes.byref(s), float(t0)))
+        ctx.sync_status()
+
+    def run(self, t_end, max_steps=1 << 40):
+        """Block steps until the next block would pass t_end; returns steps."""
+        ctx = context(self.x.device)
+        s = self._struct()
+        steps = ctypes.c_int64(0)
+        inter = ctypes.c_int64(0)
+        ctx.check(ctx.lib.nbody_blockstep(ctx.bind(), ctypes.byref(s), int(max_steps),
+                                          float(t_end), ctypes.byref(steps),
+                                          ctypes.byref(inter)))
+        self.steps += steps.value
+        self.interactions += inter.value
+        return steps.value
+
+    def step(self, n_steps=1):
+        return self.run(math.inf, max_steps=n_steps)
+
+    def energy(self):
+        K, W = energy(self.x, self.v, self.m, self.eps2)
+        return K + W

@@ -1,0 +1,143 @@
+"""Autotuner for the pair-kernel launch shapes.
+
+For a given j-count it times candidate shapes (coordinate form, i-particles
+per lane, waves per workgroup, split target) at a ladder of active-block
+sizes with HIP events, keeps the fastest per size, and installs the result
+as the context's tuning table (nbody_tune_set): each measured size covers
+the range up to the geometric midpoint with its neighbours.  Tables are
+cached as JSON next to this file, keyed by device name, j-count bucket and
+accumulation mode.
+
+Candidates use the float64-difference coordinate form (rep 0); the
+float-float form (rep 1) measured slower on gfx950 and is only tried with
+`forms=(0, 1)`; the float32-velocity form (rep 2) changes the jerk's
+accuracy and is only tried when asked for explicitly.
+"""
+from __future__ import annotations
+
+import json
+import math
+import os
+
+import torch
+
+from . import ForceShape, force, tune_clear, tune_set
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+CACHE_DIR = os.path.join(HERE, "tuned")
+
+LADDER = (1, 16, 64, 256, 1024, 4096, 16384, 65536, 262144, 1 << 20, 1 << 22)
+
+
+def _bucket(n_j: int) -> int:
+    return 1 << max(0, int(round(math.log2(max(1, n_j)))))
+
+
+def cache_path(n_j: int, mode: str) -> str:
+    name = torch.cuda.get_device_properties(0).name if torch.cuda.is_available() else "cpu"
+    arch = getattr(torch.cuda.get_device_properties(0), "gcnArchName", name).split(":")[0] \
+        if torch.cuda.is_available() else "cpu"
+    return os.path.join(CACHE_DIR, "%s_nj%d_%s.json" % (arch, _bucket(n_j), mode))
+
+
+def candidates(n_i: int, n_j: int, forms=(0,)):
+    out = []
+    for rep in forms:
+        for it in (1, 2, 4):
+            if n_i <= 64 and it > 1:
+                continue
+            for w in (1, 2, 4):
+                for tg in (8192, 32768, 65536, 131072):
+                    out.append(ForceShape(rep, it, w, 128, 64, tg))
+    return out
+
+
+def _time_shape(shape, pos, vel, mass, eps2, act, mode, reps):
+    tune_clear()
+    tune_set(0, 1 << 62, shape)
+    force(pos, vel, mass, eps2, act, mode)  # warm-up (and allocation)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        force(pos, vel, mass, eps2, act, mode)
+    e1.record()
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / reps
+
+
+def tune(pos, vel, mass, eps2, mode="fp32", ladder=None, forms=(0,),
+         budget_interactions=4e11, log=None):
+    """Measure the ladder of block sizes on the given particles.
+
+    Returns {"n_j": n, "mode": mode, "entries": [[n_i, shape_dict, ms], ...]}.
+    """
+    n = mass.shape[0]
+    ladder = [k for k in (ladder or LADDER) if k <= n]
+    if n not in ladder:
+        ladder.append(n)
+    gen = torch.Generator(device="cpu").manual_seed(12345)
+    entries = []
+    for n_i in ladder:
+        act = None if n_i == n else \
+            torch.sort(torch.randperm(n, generator=gen)[:n_i])[0].to(torch.int32).cuda()
+        work = float(n_i) * n
+        reps = int(max(1, min(20, budget_interactions / 50 / max(work, 1.0))))
+        best = None
+        for shape in candidates(n_i, n, forms):
+            ms = _time_shape(shape, pos, vel, mass, eps2, act, mode, reps)
+            if best is None or ms < best[1]:
+                best = (shape, ms)
+        entries.append([n_i, best[0].asdict(), best[1]])
+        if log:
+            log("tune n_j=%d n_i=%d: %r %.3f ms (%.3e interactions/s)"
+                % (n, n_i, best[0], best[1], work / best[1] * 1e3))
+    tune_clear()
+    return {"n_j": n, "mode": mode, "entries": entries}
+
+
+def install(table, dynamic_n_i=None):
+    """Install a tuned table into the current device's context.
+
+    Each measured n_i covers [geometric midpoint below, midpoint above).  The
+    block-step driver's shape is the one measured closest to `dynamic_n_i`
+    (default: the smallest measured size above 1).
+    """
+    tune_clear()
+    ent = sorted(table["entries"], key=lambda e: e[0])
+    sizes = [e[0] for e in ent]
+    for k, (n_i, shape, _) in enumerate(ent):
+        lo = 0 if k == 0 else int(math.sqrt(sizes[k - 1] * n_i)) + 1
+        hi = (1 << 62) if k == len(ent) - 1 else int(math.sqrt(n_i * sizes[k + 1])) + 1
+        tune_set(lo, hi, ForceShape(**shape))
+    if ent:
+        target = dynamic_n_i or (sizes[1] if len(sizes) > 1 else sizes[0])
+        pick = min(ent, key=lambda e: abs(math.log2(e[0]) - math.log2(max(1, target))))
+        tune_set(-1, 0, ForceShape(**pick[1]))
+
+
+def load(n_j, mode="fp32"):
+    p = cache_path(n_j, mode)
+    if os.path.exists(p):
+        with open(p) as f:
+            return json.load(f)
+    return None
+
+
+def save(table):
+    os.makedirs(CACHE_DIR, exist_ok=True)
+    p = cache_path(table["n_j"], table["mode"])
+    with open(p, "w") as f:
+        json.dump(table, f, indent=1)
+    return p
+
+
+def load_or_tune(pos, vel, mass, eps2, mode="fp32", log=None, dynamic_n_i=None, **kw):
+    n = mass.shape[0]
+    table = load(n, mode)
+    if table is None:
+        table = tune(pos, vel, mass, eps2, mode, log=log, **kw)
+        save(table)
+    install(table, dynamic_n_i=dynamic_n_i)
+    return table

@@ -1,0 +1,624 @@
+// Pair sums of acceleration, jerk and potential (Section 2, Eq. (1), in the
+// softened form of the Appendix A listing) on gfx950.
+//
+// Mapping (one lane per i-particle, j streamed through the scalar path):
+//   * the j side is a packed 64-byte record per particle; the j loop index
+//     is wave-uniform, so each record is fetched with scalar loads into SGPRs
+//     and every lane reads it as an instruction operand: no LDS traffic and
+//     no VGPRs for j data in the inner loop;
+//   * each lane keeps IT i-particles;
+//   * r = x_j - x_i and w = v_j - v_i are formed to float64 accuracy (see the
+//     record forms in common.hpp) and then the pair arithmetic is float32
+//     with the VALU reciprocal square root;
+//   * a wave sums `tile` consecutive j in float32, then folds the tile sum
+//     into its running sum: a float32 add (NBODY_ACC_FP32) or an exact
+//     TwoSum into a float-float pair (NBODY_ACC_DS);
+//   * the W waves of a workgroup share the same i-particles and split their
+//     j range; their sums are combined in float64 through LDS in wave order;
+//   * when the active block is too small to fill the GPU, the j range is
+//     also split across S workgroups; their float64 partial sums are added
+//     in split order by a second kernel.
+// The self pair is skipped by index: tiles whose j range can contain one of
+// the wave's own indices take a masked path.
+#include <cmath>
+
+#include "common.hpp"
+
+namespace nb {
+
+template <int REP>
+__global__ void pack_kernel(int64_t n, const double *__restrict__ pos,
+                            const double *__restrict__ vel, const double *__restrict__ mass,
+                            JRec *__restrict__ out) {
+    int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    store_rec(REP, out + i, pos[i], pos[n + i], pos[2 * n + i], vel[i], vel[n + i],
+              vel[2 * n + i], mass[i]);
+}
+
+int launch_pack(nbody_ctx *ctx, int rep, int64_t n, const double *pos, const double *vel,
+                const double *mass, JRec *out) {
+    if (n <= 0) return NBODY_OK;
+    const dim3 g((unsigned)((n + 255) / 256)), b(256);
+    if (rep == REP_FF)
+        pack_kernel<REP_FF><<<g, b, 0, ctx->stream>>>(n, pos, vel, mass, out);
+    else if (rep == REP_F64V)
+        pack_kernel<REP_F64V><<<g, b, 0, ctx->stream>>>(n, pos, vel, mass, out);
+    else
+        pack_kernel<REP_F64><<<g, b, 0, ctx->stream>>>(n, pos, vel, mass, out);
+    return hip_check(ctx, hipGetLastError(), "pack_kernel");
+}
+
+// ---- record forms: scalar-path loads and relative coordinates -------------
+#define CONSTP(T) const __attribute__((address_space(4))) T *
+
+template <int REP>
+struct Form;
+
+template <>
+struct Form<REP_F64> {
+    typedef RecF64 Rec;
+    struct I {
+        double x, y, z, u, v, w;
+    };
+    static __device__ __forceinline__ Rec load(CONSTP(JRec) base, int j) {
+        CONSTP(Rec) R = (CONSTP(Rec))base;
+        Rec r;
+        r.x = R[j].x; r.y = R[j].y; r.z = R[j].z; r.m = R[j].m;
+        r.u = R[j].u; r.v = R[j].v; r.w = R[j].w;
+        return r;
+    }
+    static __device__ __forceinline__ I own(double x, double y, double z, double u, double v,
+                                            double w) {
+        return I{x, y, z, u, v, w};
+    }
+    static __device__ __forceinline__ void rel(const Rec &r, const I &s, float &dx, float &dy,
+                                               float &dz, float &du, float &dv, float &dw) {
+        dx = (float)(r.x - s.x);
+        dy = (float)(r.y - s.y);
+        dz = (float)(r.z - s.z);
+        du = (float)(r.u - s.u);
+        dv = (float)(r.v - s.v);
+        dw = (float)(r.w - s.w);
+    }
+};
+
+template <>
+struct Form<REP_FF> {
+    typedef RecFF Rec;
+    struct I {
+        float xh, yh, zh, uh, vh, wh, xl, yl, zl, ul, vl, wl;
+    };
+    static __device__ __forceinline__ Rec load(CONSTP(JRec) base, int j) {
+        CONSTP(Rec) R = (CONSTP(Rec))base;
+        Rec r;
+        r.xh = R[j].xh; r.yh = R[j].yh; r.zh = R[j].zh; r.m = R[j].m;
+        r.uh = R[j].uh; r.vh = R[j].vh; r.wh = R[j].wh;
+        r.xl = R[j].xl; r.yl = R[j].yl; r.zl = R[j].zl;
+        r.ul = R[j].ul; r.vl = R[j].vl; r.wl = R[j].wl;
+        return r;
+    }
+    static __device__ __forceinline__ I own(double x, double y, double z, double u, double v,
+                                            double w) {
+        I s;
+        split_ff(x, s.xh, s.xl);
+        split_ff(y, s.yh, s.yl);
+        split_ff(z, s.zh, s.zl);
+        split_ff(u, s.uh, s.ul);
+        split_ff(v, s.vh, s.vl);
+        split_ff(w, s.wh, s.wl);
+        return s;
+    }
+    static __device__ __forceinline__ void rel(const Rec &r, const I &s, float &dx, float &dy,
+                                               float &dz, float &du, float &dv, float &dw) {
+        dx = (r.xh - s.xh) + (r.xl - s.xl);
+        dy = (r.yh - s.yh) + (r.yl - s.yl);
+        dz = (r.zh - s.zh) + (r.zl - s.zl);
+        du = (r.uh - s.uh) + (r.ul - s.ul);
+        dv = (r.vh - s.vh) + (r.vl - s.vl);
+        dw = (r.wh - s.wh) + (r.wl - s.wl);
+    }
+};
+
+template <>
+struct Form<REP_F64V> {
+    typedef RecF64V Rec;
+    struct I {
+        double x, y, z;
+        float u, v, w;
+    };
+    static __device__ __forceinline__ Rec load(CONSTP(JRec) base, int j) {
+        CONSTP(Rec) R = (CONSTP(Rec))base;
+        Rec r;
+        r.x = R[j].x; r.y = R[j].y; r.z = R[j].z; r.m = R[j].m;
+        r.u = R[j].u; r.v = R[j].v; r.w = R[j].w;
+        return r;
+    }
+    static __device__ __forceinline__ I own(double x, double y, double z, double u, double v,
+                                            double w) {
+        return I{x, y, z, (float)u, (float)v, (float)w};
+    }
+    static __device__ __forceinline__ void rel(const Rec &r, const I &s, float &dx, float &dy,
+                                               float &dz, float &du, float &dv, float &dw) {
+        dx = (float)(r.x - s.x);
+        dy = (float)(r.y - s.y);
+        dz = (float)(r.z - s.z);
+        du = r.u - s.u;
+        dv = r.v - s.v;
+        dw = r.w - s.w;
+    }
+};
+
+struct KArgs {
+    const JRec *__restrict__ jrec;
+    const double *__restrict__ pos;
+    const double *__restrict__ vel;
+    const int32_t *__restrict__ active;
+    const int64_t *__restrict__ n_i_dev;
+    double *__restrict__ acc;
+    double *__restrict__ jerk;
+    double *__restrict__ pot;
+    double *__restrict__ part;
+    int32_t *status;  // latched error bits (an active index out of range)
+    int64_t n_i;
+    int64_t out_stride;  // <= 0: use n_i
+    int32_t n_j;
+    float eps2;
+    int32_t tile;
+    int32_t min_j_wave;
+    int32_t target_groups;
+    int32_t max_splits;
+};
+
+// Number of workgroups that share one i-block's j range.
+__host__ __device__ inline int64_t choose_splits(int64_t n_i, int64_t n_j, int it, int waves,
+                                                 int min_j_wave, int target_groups,
+                                                 int max_splits) {
+    int64_t nb = (n_i + 64 * it - 1) / (64 * it);
+    if (nb < 1) nb = 1;
+    int64_t s = (target_groups + nb - 1) / nb;
+    int64_t smax = n_j / ((int64_t)waves * min_j_wave);
+    if (smax > max_splits) smax = max_splits;
+    if (s > smax) s = smax;
+    if (s < 1) s = 1;
+    return s;
+}
+
+__device__ __forceinline__ void two_sum_acc(float &hi, float &lo, float x) {
+    const float s = hi + x;
+    const float bp = s - hi;
+    const float e = (hi - (s - bp)) + (x - bp);
+    hi = s;
+    lo += e;
+}
+
+__device__ __forceinline__ int wave_min(int v) {
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) v = min(v, __shfl_xor(v, o, 64));
+    return v;
+}
+__device__ __forceinline__ int wave_max(int v) {
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) v = max(v, __shfl_xor(v, o, 64));
+    return v;
+}
+
+template <int REP, int IT, int W, bool DS>
+__global__ __launch_bounds__(64 * W) void force_kernel(const KArgs a) {
+    typedef Form<REP> F;
+    typedef typename F::Rec Rec;
+    const int64_t n_i = a.n_i_dev ? *a.n_i_dev : a.n_i;
+    if (n_i <= 0) return;
+    const int n_j = a.n_j;
+    const int64_t ostride = a.out_stride > 0 ? a.out_stride : n_i;
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int64_t nb = (n_i + 64 * IT - 1) / (64 * IT);
+    const int64_t S = choose_splits(n_i, n_j, IT, W, a.min_j_wave, a.target_groups, a.max_splits);
+    const int64_t items = nb * S;
+    const int64_t jchunk = (n_j + S - 1) / S;
+    const float eps2 = a.eps2;
+    const int tile = a.tile;
+    // Constant address space: the records are read-only during the kernel
+    // and their addresses are wave-uniform, so every field is fetched with a
+    // scalar load into SGPRs.
+    const CONSTP(JRec) J = (CONSTP(JRec))a.jrec;
+
+    __shared__ double red[W > 1 ? W - 1 : 1][7 * IT][64];
+
+    for (int64_t item = blockIdx.x; item < items; item += gridDim.x) {
+        const int64_t ib = item % nb;
+        const int64_t sp = item / nb;
+        const int j0 = (int)(sp * jchunk);
+        const int j1 = (int)min((int64_t)n_j, (int64_t)j0 + jchunk);
+        const int jw = (j1 - j0 + W - 1) / W;
+        const int jb = __builtin_amdgcn_readfirstlane(min(j1, j0 + wave * jw));
+        const int je = __builtin_amdgcn_readfirstlane(min(j1, jb + jw));
+
+        typename F::I own[IT];
+        int idx[IT];
+        int64_t slot[IT];
+        int lo_idx = 0x7fffffff, hi_idx = -1;
+#pragma unroll
+        for (int t = 0; t < IT; ++t) {
+            slot[t] = ib * (64 * IT) + t * 64 + lane;
+            const int64_t sl = slot[t] < n_i ? slot[t] : n_i - 1;
+            idx[t] = a.active ? a.active[sl] : (int)sl;
+            if ((unsigned)idx[t] >= (unsigned)n_j) {
+                atomicOr(a.status, (int32_t)ST_INDEX);
+                idx[t] = 0;
+            }
+            const int64_t q = idx[t];
+            own[t] = F::own(a.pos[q], a.pos[n_j + q], a.pos[2 * (int64_t)n_j + q], a.vel[q],
+                            a.vel[n_j + q], a.vel[2 * (int64_t)n_j + q]);
+            lo_idx = min(lo_idx, idx[t]);
+            hi_idx = max(hi_idx, idx[t]);
+        }
+        lo_idx = __builtin_amdgcn_readfirstlane(wave_min(lo_idx));
+        hi_idx = __builtin_amdgcn_readfirstlane(wave_max(hi_idx));
+
+        // running sums: hi parts (and lo parts for DS); the potential is
+        // accumulated as +sum m/r and negated when stored
+        float sax[IT], say[IT], saz[IT], sjx[IT], sjy[IT], sjz[IT], sph[IT];
+        float lax[IT], lay[IT], laz[IT], ljx[IT], ljy[IT], ljz[IT], lph[IT];
+#pragma unroll
+        for (int t = 0; t < IT; ++t) {
+            sax[t] = say[t] = saz[t] = sjx[t] = sjy[t] = sjz[t] = sph[t] = 0.0f;
+            lax[t] = lay[t] = laz[t] = ljx[t] = ljy[t] = ljz[t] = lph[t] = 0.0f;
+        }
+
+        for (int jt = jb; jt < je; jt += tile) {
+            const int jend = min(je, jt + tile);
+            float iax[IT], iay[IT], iaz[IT], ijx[IT], ijy[IT], ijz[IT], iph[IT];
+#pragma unroll
+            for (int t = 0; t < IT; ++t)
+                iax[t] = iay[t] = iaz[t] = ijx[t] = ijy[t] = ijz[t] = iph[t] = 0.0f;
+
+            auto body = [&](const Rec &r, const int j, const bool mask)
+                __attribute__((always_inline)) {
+#pragma unroll
+                for (int t = 0; t < IT; ++t) {
+                    float dx, dy, dz, du, dv, dw;
+                    F::rel(r, own[t], dx, dy, dz, du, dv, dw);
+                    float s2 = fmaf(dz, dz, fmaf(dy, dy, fmaf(dx, dx, eps2)));
+                    float mj = r.m;
+                    if (mask) {
+                        const bool self = (j == idx[t]);
+                        s2 = self ? 1.0f : s2;
+                        mj = self ? 0.0f : mj;
+                    }
+                    const float rv = fmaf(dz, dw, fmaf(dy, dv, dx * du));
+                    const float rinv = __builtin_amdgcn_rsqf(s2);
+                    const float rinv2 = rinv * rinv;
+                    const float mr1 = mj * rinv;
+                    const float mr3 = mr1 * rinv2;
+                    const float w3 = (rv * rinv2) * -3.0f;
+                    iax[t] = fmaf(mr3, dx, iax[t]);
+                    iay[t] = fmaf(mr3, dy, iay[t]);
+                    iaz[t] = fmaf(mr3, dz, iaz[t]);
+                    ijx[t] = fmaf(mr3, fmaf(w3, dx, du), ijx[t]);
+                    ijy[t] = fmaf(mr3, fmaf(w3, dy, dv), ijy[t]);
+                    ijz[t] = fmaf(mr3, fmaf(w3, dz, dw), ijz[t]);
+                    iph[t] = fmaf(mj, rinv, iph[t]);
+                }
+            };
+
+            if (jt <= hi_idx && jend > lo_idx) {
+                for (int j = jt; j < jend; ++j) {
+                    const Rec r = F::load(J, j);
+                    body(r, j, true);
+                }
+            } else {
+                // software pipelined: the next record's scalar loads are in
+                // flight while the current one is used
+                Rec cur = F::load(J, jt);
+#pragma unroll 4
+                for (int j = jt; j < jend; ++j) {
+                    const Rec nxt = F::load(J, min(j + 1, jend - 1));
+                    body(cur, j, false);
+                    cur = nxt;
+                }
+            }
+
+#pragma unroll
+            for (int t = 0; t < IT; ++t) {
+                if (DS) {
+                    two_sum_acc(sax[t], lax[t], iax[t]);
+                    two_sum_acc(say[t], lay[t], iay[t]);
+                    two_sum_acc(saz[t], laz[t], iaz[t]);
+                    two_sum_acc(sjx[t], ljx[t], ijx[t]);
+                    two_sum_acc(sjy[t], ljy[t], ijy[t]);
+                    two_sum_acc(sjz[t], ljz[t], ijz[t]);
+                    two_sum_acc(sph[t], lph[t], iph[t]);
+                } else {
+                    sax[t] += iax[t];
+                    say[t] += iay[t];
+                    saz[t] += iaz[t];
+                    sjx[t] += ijx[t];
+                    sjy[t] += ijy[t];
+                    sjz[t] += ijz[t];
+                    sph[t] += iph[t];
+                }
+            }
+        }
+
+        // per-wave totals in float64 (hi + lo is exact in float64)
+        double tot[IT][7];
+#pragma unroll
+        for (int t = 0; t < IT; ++t) {
+            tot[t][0] = (double)sax[t] + (double)lax[t];
+            tot[t][1] = (double)say[t] + (double)lay[t];
+            tot[t][2] = (double)saz[t] + (double)laz[t];
+            tot[t][3] = (double)sjx[t] + (double)ljx[t];
+            tot[t][4] = (double)sjy[t] + (double)ljy[t];
+            tot[t][5] = (double)sjz[t] + (double)ljz[t];
+            tot[t][6] = -((double)sph[t] + (double)lph[t]);
+        }
+        if (W > 1) {
+            if (wave > 0) {
+#pragma unroll
+                for (int t = 0; t < IT; ++t)
+#pragma unroll
+                    for (int q = 0; q < 7; ++q) red[wave - 1][t * 7 + q][lane] = tot[t][q];
+            }
+            __syncthreads();
+            if (wave == 0) {
+                for (int w = 1; w < W; ++w)
+#pragma unroll
+                    for (int t = 0; t < IT; ++t)
+#pragma unroll
+                        for (int q = 0; q < 7; ++q) tot[t][q] += red[w - 1][t * 7 + q][lane];
+            }
+        }
+        if (wave == 0) {
+#pragma unroll
+            for (int t = 0; t < IT; ++t) {
+                if (slot[t] < n_i) {
+                    const int64_t s = slot[t];
+                    if (S == 1) {
+                        a.acc[s] = tot[t][0];
+                        a.acc[ostride + s] = tot[t][1];
+                        a.acc[2 * ostride + s] = tot[t][2];
+                        a.jerk[s] = tot[t][3];
+                        a.jerk[ostride + s] = tot[t][4];
+                        a.jerk[2 * ostride + s] = tot[t][5];
+                        if (a.pot) a.pot[s] = tot[t][6];
+                    } else {
+                        double *p = a.part + (sp * 7) * n_i + s;
+#pragma unroll
+                        for (int q = 0; q < 7; ++q) p[q * n_i] = tot[t][q];
+                    }
+                }
+            }
+        }
+        if (W > 1) __syncthreads();
+    }
+}
+
+// Adds the S float64 partial sums of every output in a fixed order: the 64
+// lanes of a wave take 64 consecutive outputs, the RW waves of a workgroup
+// take contiguous quarters of the splits, and the wave sums are combined in
+// wave order through LDS.
+constexpr int RW = 8;
+__global__ __launch_bounds__(64 * RW) void reduce_parts_kernel(const KArgs a, int it, int waves) {
+    __shared__ double red[RW][64];
+    const int64_t n_i = a.n_i_dev ? *a.n_i_dev : a.n_i;
+    if (n_i <= 0) return;
+    const int64_t S = choose_splits(n_i, a.n_j, it, waves, a.min_j_wave, a.target_groups,
+                                    a.max_splits);
+    if (S == 1) return;
+    const int64_t ostride = a.out_stride > 0 ? a.out_stride : n_i;
+    const int64_t total = 7 * n_i;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int64_t per = (S + RW - 1) / RW;
+    const int64_t p0 = wave * per, p1 = min(S, p0 + per);
+    for (int64_t base = blockIdx.x * (int64_t)64; base < total; base += (int64_t)gridDim.x * 64) {
+        const int64_t e = base + lane;
+        double acc = 0.0;
+        if (e < total) {
+            const int64_t q = e / n_i, s = e - q * n_i;
+            const double *src = a.part + q * n_i + s;
+            for (int64_t p = p0; p < p1; ++p) acc += src[p * 7 * n_i];
+        }
+        red[wave][lane] = acc;
+        __syncthreads();
+        if (wave == 0 && e < total) {
+            double t = red[0][lane];
+            for (int w = 1; w < RW; ++w) t += red[w][lane];
+            const int64_t q = e / n_i, s = e - q * n_i;
+            if (q < 3)
+                a.acc[q * ostride + s] = t;
+            else if (q < 6)
+                a.jerk[(q - 3) * ostride + s] = t;
+            else if (a.pot)
+                a.pot[s] = t;
+        }
+        __syncthreads();
+    }
+}
+
+typedef void (*force_fn)(const KArgs);
+
+template <int REP, int IT, bool DS>
+static force_fn pick_w(int w) {
+    switch (w) {
+        case 1: return force_kernel<REP, IT, 1, DS>;
+        case 2: return force_kernel<REP, IT, 2, DS>;
+        case 4: return force_kernel<REP, IT, 4, DS>;
+        case 8: return force_kernel<REP, IT, 8, DS>;
+        default: return nullptr;
+    }
+}
+
+template <int REP, bool DS>
+static force_fn pick_w4(int w) {
+    switch (w) {
+        case 1: return force_kernel<REP, 4, 1, DS>;
+        case 2: return force_kernel<REP, 4, 2, DS>;
+        case 4: return force_kernel<REP, 4, 4, DS>;
+        default: return nullptr;
+    }
+}
+
+template <int REP>
+static force_fn pick_it(int it, int w, bool ds) {
+    if (it == 1) return ds ? pick_w<REP, 1, true>(w) : pick_w<REP, 1, false>(w);
+    if (it == 2) return ds ? pick_w<REP, 2, true>(w) : pick_w<REP, 2, false>(w);
+    if (it == 4) return ds ? pick_w4<REP, true>(w) : pick_w4<REP, false>(w);
+    return nullptr;
+}
+
+static force_fn pick_kernel(const ForceShape &s, bool ds) {
+    switch (s.rep) {
+        case REP_F64: return pick_it<REP_F64>(s.it, s.waves, ds);
+        case REP_FF: return pick_it<REP_FF>(s.it, s.waves, ds);
+        case REP_F64V: return pick_it<REP_F64V>(s.it, s.waves, ds);
+        default: return nullptr;
+    }
+}
+
+static const int kMaxSplits = 1024;
+
+static ForceShape default_shape(const nbody_ctx *ctx) {
+    ForceShape s;
+    s.rep = REP_F64;
+    s.it = 1;
+    s.waves = 4;
+    s.tile = 128;
+    s.min_j_wave = 64;
+    s.target_groups = 8 * ctx->cus;
+    return s;
+}
+
+ForceShape pick_shape(const nbody_ctx *ctx, int64_t n_i, int64_t n_j) {
+    (void)n_j;
+    for (const TuneEntry &e : ctx->tune)
+        if (e.n_i_lo >= 0 && n_i >= e.n_i_lo && n_i < e.n_i_hi) return e.shape;
+    return default_shape(ctx);
+}
+
+ForceShape dynamic_shape(const nbody_ctx *ctx, int64_t n) {
+    (void)n;
+    for (const TuneEntry &e : ctx->tune)
+        if (e.n_i_lo < 0) return e.shape;
+    return default_shape(ctx);
+}
+
+int launch_force(nbody_ctx *ctx, const ForceCall &c) {
+    const bool dev_count = c.n_i_dev != nullptr;
+    const int64_t n_i_max = dev_count ? c.n_i_cap : c.n_i;
+    if (n_i_max <= 0) return NBODY_OK;
+    const ForceShape &sh = c.shape;
+    force_fn fn = pick_kernel(sh, c.ds);
+    if (!fn)
+        return fail(ctx, NBODY_E_INVAL, "no pair kernel for rep=%d it=%d waves=%d", sh.rep, sh.it,
+                    sh.waves);
+
+    KArgs a;
+    a.jrec = c.jrec;
+    a.pos = c.pos;
+    a.vel = c.vel;
+    a.active = c.active;
+    a.n_i_dev = c.n_i_dev;
+    a.acc = c.acc;
+    a.jerk = c.jerk;
+    a.pot = c.pot;
+    a.part = nullptr;
+    a.status = &ctx->info->status;
+    a.n_i = c.n_i;
+    a.out_stride = c.out_stride;
+    a.n_j = (int32_t)c.n_j;
+    a.eps2 = (float)c.eps2;
+    a.tile = sh.tile;
+    a.min_j_wave = sh.min_j_wave;
+    a.target_groups = sh.target_groups;
+    a.max_splits = kMaxSplits;
+
+    // Partial-sum scratch: S * 7 * n_i doubles.  When S > 1 the number of
+    // i-blocks is below target_groups, so S * n_i <= 2 * target_groups * 64 * it.
+    const int64_t bi = 64 * sh.it;
+    int64_t items, need_part;
+    if (dev_count) {
+        need_part = 2 * (int64_t)sh.target_groups * bi * 7 * (int64_t)sizeof(double);
+        // Upper bound of nb * S over every block size up to n_i_cap, so that
+        // each item gets its own workgroup (dispatch order = item order, which
+        // keeps the concurrently running groups on one or two j chunks).
+        const int64_t nb_max = (n_i_max + bi - 1) / bi;
+        int64_t smax = c.n_j / ((int64_t)sh.waves * sh.min_j_wave);
+        if (smax > kMaxSplits) smax = kMaxSplits;
+        if (smax < 1) smax = 1;
+        const int64_t tg = sh.target_groups;
+        int64_t a1 = (tg + smax - 1) / smax;  // below this nb, S = smax
+        if (a1 > nb_max) a1 = nb_max;
+        items = a1 * smax;
+        int64_t b2 = tg + nb_max;             // nb * ceil(tg / nb) < tg + nb
+        if (b2 > nb_max * smax) b2 = nb_max * smax;
+        if (b2 > items) items = b2;
+        if (nb_max > items) items = nb_max;
+        if (items > (1 << 24)) items = 1 << 24;
+    } else {
+        int64_t S = choose_splits(c.n_i, c.n_j, sh.it, sh.waves, sh.min_j_wave,
+                                  sh.target_groups, kMaxSplits);
+        int64_t nb = (c.n_i + bi - 1) / bi;
+        items = nb * S;
+        need_part = S > 1 ? S * 7 * c.n_i * (int64_t)sizeof(double) : 0;
+        if (items > (1 << 24)) items = 1 << 24;
+    }
+    if (need_part > 0) {
+        NB_TRY(ensure(ctx, &ctx->part, &ctx->part_bytes, (size_t)need_part));
+        a.part = (double *)ctx->part;
+    }
+    hipEvent_t e0 = ctx->prof.on ? prof_mark(ctx) : nullptr;
+    hipLaunchKernelGGL(fn, dim3((unsigned)items), dim3(64 * sh.waves), 0, ctx->stream, a);
+    NB_TRY(hip_check(ctx, hipGetLastError(), "force_kernel"));
+    if (ctx->prof.on) prof_push(ctx, e0, prof_mark(ctx), 0);
+    if (need_part > 0) {
+        int64_t blocks = (7 * n_i_max + 63) / 64;
+        if (blocks > 16 * (int64_t)ctx->cus) blocks = 16 * (int64_t)ctx->cus;
+        if (blocks < 1) blocks = 1;
+        hipEvent_t r0 = ctx->prof.on ? prof_mark(ctx) : nullptr;
+        hipLaunchKernelGGL(reduce_parts_kernel, dim3((unsigned)blocks), dim3(64 * RW), 0,
+                           ctx->stream, a, sh.it, sh.waves);
+        NB_TRY(hip_check(ctx, hipGetLastError(), "reduce_parts_kernel"));
+        if (ctx->prof.on) prof_push(ctx, r0, prof_mark(ctx), 1);
+    }
+    return NBODY_OK;
+}
+
+}  // namespace nb
+
+using namespace nb;
+
+extern "C" int nbody_force(nbody_ctx *ctx, const int32_t *active_idx, int64_t n_i,
+                           const double *pos, const double *vel, const double *mass,
+                           int64_t n_j, double eps2, double *acc, double *jerk, double *pot,
+                           uint32_t flags) {
+    if (!ctx) return NBODY_E_INVAL;
+    if (n_i < 0 || n_j < 1 || n_i > 0x7fffffffLL || n_j > 0x7fffffffLL)
+        return fail(ctx, NBODY_E_INVAL, "nbody_force: bad sizes n_i=%lld n_j=%lld",
+                    (long long)n_i, (long long)n_j);
+    if (!(eps2 >= 0.0) || std::isinf(eps2))
+        return fail(ctx, NBODY_E_INVAL, "nbody_force: eps2 must be finite and >= 0");
+    if (flags & ~NBODY_ACC_DS) return fail(ctx, NBODY_E_INVAL, "nbody_force: unknown flags");
+    if (!pos || !vel || !mass || (n_i > 0 && (!acc || !jerk)))
+        return fail(ctx, NBODY_E_INVAL, "nbody_force: null array");
+    if (n_i == 0) return NBODY_OK;
+    NB_TRY(activate(ctx));
+    ForceCall c;
+    c.shape = pick_shape(ctx, n_i, n_j);
+    NB_TRY(ensure(ctx, &ctx->jrec, &ctx->jrec_bytes, (size_t)n_j * sizeof(JRec)));
+    NB_TRY(launch_pack(ctx, c.shape.rep, n_j, pos, vel, mass, (JRec *)ctx->jrec));
+    c.jrec = (const JRec *)ctx->jrec;
+    c.n_j = n_j;
+    c.pos = pos;
+    c.vel = vel;
+    c.active = active_idx;
+    c.n_i = n_i;
+    c.eps2 = eps2;
+    c.acc = acc;
+    c.jerk = jerk;
+    c.pot = pot;
+    c.out_stride = n_i;
+    c.ds = (flags & NBODY_ACC_DS) != 0;
+    return launch_force(ctx, c);
+}

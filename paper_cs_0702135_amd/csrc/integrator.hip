@@ -1,0 +1,599 @@
+// Hermite predictor / corrector, block scheduler, time steps, energy and
+// the device-resident block-step driver (Section 2).  All float64; the
+// predictor and corrector are compiled without contraction so that their
+// results follow the printed formulas operation by operation.
+#include <cmath>
+
+#include "common.hpp"
+
+namespace nb {
+
+static inline unsigned grid_for(int64_t n, int threads, int64_t cap) {
+    int64_t g = (n + threads - 1) / threads;
+    if (g > cap) g = cap;
+    if (g < 1) g = 1;
+    return (unsigned)g;
+}
+
+__device__ __forceinline__ void latch(StepInfo *info, int32_t bits) {
+    if (info) atomicOr(&info->status, bits);
+}
+
+// ---------------------------------------------------------------- predictor
+__global__ void predict_kernel(int64_t n, double t_target, const StepInfo *__restrict__ info,
+                               const double *__restrict__ t, const double *__restrict__ x,
+                               const double *__restrict__ v, const double *__restrict__ a,
+                               const double *__restrict__ k, double *__restrict__ xp,
+                               double *__restrict__ vp, const double *__restrict__ mass,
+                               JRec *__restrict__ jrec, int rep) {
+#pragma clang fp contract(off)
+    if (info && info->done) return;
+    const double tt = info ? info->t_next : t_target;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const double h = tt - t[i];
+        double px[3], pv[3];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            const int64_t q = c * n + i;
+            px[c] = x[q] + (v[q] + (h / 2.0) * (a[q] + (h / 3.0) * k[q])) * h;
+            pv[c] = v[q] + (a[q] + (h / 2.0) * k[q]) * h;
+            xp[q] = px[c];
+            vp[q] = pv[c];
+        }
+        if (jrec) {
+            store_rec(rep, jrec + i, px[0], px[1], px[2], pv[0], pv[1], pv[2], mass[i]);
+        }
+    }
+}
+
+// ---------------------------------------------------------------- scheduler
+// t_next = min(t + dt) by a grid-wide reduction whose last-arriving block
+// finishes it; then a count / scan / compaction pass that writes the active
+// indices in ascending order.  min is exact, and the scan works on integer
+// counts in block order, so the result is independent of timing.
+__global__ __launch_bounds__(256) void sched_min_kernel(int64_t n, const double *__restrict__ t,
+                                                        const double *__restrict__ dt,
+                                                        double *__restrict__ partial,
+                                                        StepInfo *__restrict__ info) {
+    __shared__ double red[256];
+    __shared__ bool last;
+    double m = INFINITY;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x)
+        m = fmin(m, t[i] + dt[i]);
+    red[threadIdx.x] = m;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+        if ((int)threadIdx.x < o) red[threadIdx.x] = fmin(red[threadIdx.x], red[threadIdx.x + o]);
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        partial[blockIdx.x] = red[0];
+        __threadfence();
+        unsigned tk = __hip_atomic_fetch_add(&info->ticket0, 1u, __ATOMIC_ACQ_REL,
+                                             __HIP_MEMORY_SCOPE_AGENT);
+        last = (tk == gridDim.x - 1);
+    }
+    __syncthreads();
+    if (!last) return;
+    __threadfence();
+    m = INFINITY;
+    for (unsigned b = threadIdx.x; b < gridDim.x; b += blockDim.x)
+        m = fmin(m, __builtin_nontemporal_load(&partial[b]));
+    red[threadIdx.x] = m;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+        if ((int)threadIdx.x < o) red[threadIdx.x] = fmin(red[threadIdx.x], red[threadIdx.x + o]);
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        const double tn = red[0];
+        info->t_next = tn;
+        const bool done = !(tn <= info->t_end);
+        info->done = done ? 1 : 0;
+        if (done) info->n_i = 0;
+        __hip_atomic_store(&info->ticket0, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+}
+
+__device__ __forceinline__ bool is_active(const double *t, const double *dt, int64_t i,
+                                          double tn) {
+    return t[i] + dt[i] == tn;
+}
+
+__global__ __launch_bounds__(256) void sched_count_kernel(
+    int64_t n, const double *__restrict__ t, const double *__restrict__ dt,
+    int64_t *__restrict__ counts, StepInfo *__restrict__ info, int count_steps,
+    int64_t *__restrict__ n_i_out, double *__restrict__ t_next_out) {
+    __shared__ int64_t red[256];
+    __shared__ bool last;
+    if (info->done) {
+        if (blockIdx.x == 0 && threadIdx.x == 0) {
+            if (n_i_out) *n_i_out = 0;
+            if (t_next_out) *t_next_out = info->t_next;
+        }
+        return;
+    }
+    const double tn = info->t_next;
+    const int64_t chunk = (n + gridDim.x - 1) / gridDim.x;
+    const int64_t lo = blockIdx.x * chunk;
+    const int64_t hi = lo + chunk < n ? lo + chunk : n;
+    int64_t c = 0;
+    for (int64_t i = lo + threadIdx.x; i < hi; i += blockDim.x) c += is_active(t, dt, i, tn);
+    red[threadIdx.x] = c;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+        if ((int)threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        counts[blockIdx.x] = red[0];
+        __threadfence();
+        unsigned tk = __hip_atomic_fetch_add(&info->ticket1, 1u, __ATOMIC_ACQ_REL,
+                                             __HIP_MEMORY_SCOPE_AGENT);
+        last = (tk == gridDim.x - 1);
+    }
+    __syncthreads();
+    if (!last) return;
+    __threadfence();
+    // exclusive scan of the per-block counts (gridDim.x <= 1024), in block
+    // order: each thread scans 4 consecutive counts, then a block scan of the
+    // 256 thread totals
+    __shared__ int64_t tsum[256];
+    int64_t cb[4], run = 0;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const unsigned b = threadIdx.x * 4 + q;
+        cb[q] = b < gridDim.x ? __builtin_nontemporal_load(&counts[b]) : 0;
+        run += cb[q];
+    }
+    tsum[threadIdx.x] = run;
+    __syncthreads();
+    for (int o = 1; o < 256; o <<= 1) {
+        const int64_t v = (int)threadIdx.x >= o ? tsum[threadIdx.x - o] : 0;
+        __syncthreads();
+        tsum[threadIdx.x] += v;
+        __syncthreads();
+    }
+    int64_t off = tsum[threadIdx.x] - run;  // exclusive prefix of this thread
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const unsigned b = threadIdx.x * 4 + q;
+        if (b < gridDim.x) counts[b] = off;
+        off += cb[q];
+    }
+    if (threadIdx.x == 255) {
+        const int64_t total = tsum[255];
+        info->n_i = total;
+        if (count_steps) {
+            info->steps += 1;
+            info->interactions += total * n;
+        }
+        if (n_i_out) *n_i_out = total;
+        if (t_next_out) *t_next_out = tn;
+        __hip_atomic_store(&info->ticket1, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+}
+
+__global__ __launch_bounds__(256) void sched_compact_kernel(int64_t n,
+                                                            const double *__restrict__ t,
+                                                            const double *__restrict__ dt,
+                                                            const int64_t *__restrict__ offsets,
+                                                            const StepInfo *__restrict__ info,
+                                                            int32_t *__restrict__ active) {
+    __shared__ int wsum[4];
+    if (info->done) return;
+    const double tn = info->t_next;
+    const int64_t chunk = (n + gridDim.x - 1) / gridDim.x;
+    const int64_t lo = blockIdx.x * chunk;
+    const int64_t hi = lo + chunk < n ? lo + chunk : n;
+    int64_t base = offsets[blockIdx.x];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    for (int64_t p = lo; p < hi; p += blockDim.x) {
+        const int64_t i = p + threadIdx.x;
+        const bool f = i < hi && is_active(t, dt, i, tn);
+        const unsigned long long bal = __ballot(f);
+        const int before = __popcll(bal & ((1ull << lane) - 1ull));
+        if (lane == 0) wsum[wave] = __popcll(bal);
+        __syncthreads();
+        int woff = 0, tot = 0;
+        for (int w = 0; w < 4; ++w) {
+            if (w < wave) woff += wsum[w];
+            tot += wsum[w];
+        }
+        if (f) active[base + woff + before] = (int32_t)i;
+        base += tot;
+        __syncthreads();
+    }
+}
+
+static int sched_grids(int64_t n, unsigned *g1, unsigned *g2) {
+    *g1 = grid_for(n, 256 * 8, 1024);
+    *g2 = grid_for(n, 1024, 1024);
+    return NBODY_OK;
+}
+
+static int launch_schedule(nbody_ctx *ctx, int64_t n, const double *t, const double *dt,
+                           int32_t *active, int count_steps, int64_t *n_i_out,
+                           double *t_next_out) {
+    unsigned g1, g2;
+    sched_grids(n, &g1, &g2);
+    NB_TRY(ensure(ctx, &ctx->work, &ctx->work_bytes, 2048 * sizeof(double)));
+    double *partial = (double *)ctx->work;
+    int64_t *counts = (int64_t *)ctx->work + 1024;
+    sched_min_kernel<<<g1, 256, 0, ctx->stream>>>(n, t, dt, partial, ctx->info);
+    sched_count_kernel<<<g2, 256, 0, ctx->stream>>>(n, t, dt, counts, ctx->info, count_steps,
+                                                    n_i_out, t_next_out);
+    sched_compact_kernel<<<g2, 256, 0, ctx->stream>>>(n, t, dt, counts, ctx->info, active);
+    return hip_check(ctx, hipGetLastError(), "scheduler");
+}
+
+__global__ void set_info_kernel(StepInfo *info, double t_end, int reset_counters) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) {
+        info->t_end = t_end;
+        info->done = 0;
+        if (reset_counters) {
+            info->steps = 0;
+            info->interactions = 0;
+        }
+    }
+}
+
+// ---------------------------------------------------------------- corrector
+__global__ void correct_kernel(int64_t n, int64_t n_i_arg, const StepInfo *__restrict__ cinfo,
+                               StepInfo *__restrict__ sinfo, const int32_t *__restrict__ active,
+                               const double *__restrict__ xp, const double *__restrict__ vp,
+                               const double *__restrict__ acc_new,
+                               const double *__restrict__ jerk_new, int64_t stride_new,
+                               double eta, double dt_max, double dt_min, int fixed_dt,
+                               double *__restrict__ t, double *__restrict__ dtv,
+                               double *__restrict__ x, double *__restrict__ v,
+                               double *__restrict__ a, double *__restrict__ k) {
+#pragma clang fp contract(off)
+    const int64_t n_i = cinfo ? cinfo->n_i : n_i_arg;
+    const int64_t sn = stride_new > 0 ? stride_new : n_i;
+    for (int64_t s = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; s < n_i;
+         s += (int64_t)gridDim.x * blockDim.x) {
+        int64_t i = active ? (int64_t)active[s] : s;
+        if (i < 0 || i >= n) {
+            latch(sinfo, ST_INDEX);
+            continue;
+        }
+        const double h = dtv[i];
+        const double t_new = t[i] + h;
+        double a1v[3], k1v[3], a2v[3], a3v[3];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            const int64_t q = c * n + i;
+            const double a0 = a[q], k0 = k[q];
+            const double a1 = acc_new[c * sn + s], k1 = jerk_new[c * sn + s];
+            const double A3 = 2.0 * (a0 - a1) + (k0 + k1) * h;
+            const double A2 = -3.0 * (a0 - a1) - (2.0 * k0 + k1) * h;
+            x[q] = xp[q] + (A2 / 12.0 + A3 / 20.0) * h * h;
+            v[q] = vp[q] + (A2 / 3.0 + A3 / 4.0) * h;
+            a[q] = a1;
+            k[q] = k1;
+            a1v[c] = a1;
+            k1v[c] = k1;
+            a2v[c] = (2.0 * A2 + 6.0 * A3) / (h * h);
+            a3v[c] = 6.0 * A3 / (h * h * h);
+        }
+        t[i] = t_new;
+        if (!fixed_dt) {
+            const double an = sqrt(a1v[0] * a1v[0] + a1v[1] * a1v[1] + a1v[2] * a1v[2]);
+            const double kn = sqrt(k1v[0] * k1v[0] + k1v[1] * k1v[1] + k1v[2] * k1v[2]);
+            const double a2n = sqrt(a2v[0] * a2v[0] + a2v[1] * a2v[1] + a2v[2] * a2v[2]);
+            const double a3n = sqrt(a3v[0] * a3v[0] + a3v[1] * a3v[1] + a3v[2] * a3v[2]);
+            const double num = eta * (an * a2n + kn * kn);
+            const double den = kn * a3n + a2n * a2n;
+            double crit = den > 0.0 ? sqrt(num / den) : INFINITY;
+            double d = h;
+            if (!(crit == crit)) {
+                latch(sinfo, ST_NONFINITE);
+                crit = d;
+            }
+            if (d > crit) {
+                while (d > crit) d = d / 2.0;
+            } else if (2.0 * d <= crit && fmod(t_new, 2.0 * d) == 0.0 && 2.0 * d <= dt_max) {
+                d = 2.0 * d;
+            }
+            if (d < dt_min) {
+                latch(sinfo, ST_RANGE);
+                d = dt_min;
+            }
+            dtv[i] = d;
+        }
+    }
+}
+
+// ------------------------------------------------------------ initial steps
+__global__ void initial_dt_kernel(int64_t n, double t0, const double *__restrict__ a,
+                                  const double *__restrict__ k, double eta_s, double dt_max,
+                                  double dt_min, double *__restrict__ dt, StepInfo *info) {
+#pragma clang fp contract(off)
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const double ax = a[i], ay = a[n + i], az = a[2 * n + i];
+        const double kx = k[i], ky = k[n + i], kz = k[2 * n + i];
+        const double an = sqrt(ax * ax + ay * ay + az * az);
+        const double kn = sqrt(kx * kx + ky * ky + kz * kz);
+        double want = kn > 0.0 ? eta_s * an / kn : dt_max;
+        if (!(want == want)) {
+            latch(info, ST_NONFINITE);
+            want = dt_min;
+        }
+        double d = dt_max;
+        while (d > want && d >= 2.0 * dt_min) d = d / 2.0;
+        while (fmod(t0, d) != 0.0 && d >= 2.0 * dt_min) d = d / 2.0;
+        if (d > want || fmod(t0, d) != 0.0) latch(info, ST_RANGE);
+        dt[i] = d;
+    }
+}
+
+__global__ void fill_kernel(int64_t n, double v, double *__restrict__ out) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x)
+        out[i] = v;
+}
+
+// ------------------------------------------------------------------ energy
+// phi_i = -sum_{j != i} m_j / sqrt(|x_j - x_i|^2 + eps2) in float64, one
+// lane per i, j wave-uniform; K and W are reduced per block in a fixed tree
+// and across blocks in block order by the last block to finish.
+__global__ __launch_bounds__(256) void energy_kernel(int64_t n, const double *__restrict__ pos,
+                                                     const double *__restrict__ vel,
+                                                     const double *__restrict__ mass,
+                                                     double eps2, double *__restrict__ partial,
+                                                     StepInfo *__restrict__ info,
+                                                     double *__restrict__ out) {
+    __shared__ double rk[256], rw[256];
+    __shared__ bool last;
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    double kin = 0.0, wpot = 0.0;
+    // j-side reads through the constant address space: wave-uniform scalar loads
+    typedef const __attribute__((address_space(4))) double *CD;
+    const CD pk = (CD)pos;
+    const CD mk = (CD)mass;
+    if (i < n) {
+        const double xi = pos[i], yi = pos[n + i], zi = pos[2 * n + i];
+        double ph = 0.0;
+        for (int64_t j = 0; j < n; ++j) {
+            const double rx = pk[j] - xi, ry = pk[n + j] - yi, rz = pk[2 * n + j] - zi;
+            const double term = mk[j] / sqrt(rx * rx + ry * ry + rz * rz + eps2);
+            ph -= (j == i) ? 0.0 : term;
+        }
+        const double u = vel[i], w = vel[n + i], z = vel[2 * n + i];
+        kin = 0.5 * mass[i] * (u * u + w * w + z * z);
+        wpot = mass[i] * ph;
+    }
+    rk[threadIdx.x] = kin;
+    rw[threadIdx.x] = wpot;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+        if ((int)threadIdx.x < o) {
+            rk[threadIdx.x] += rk[threadIdx.x + o];
+            rw[threadIdx.x] += rw[threadIdx.x + o];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        partial[2 * blockIdx.x] = rk[0];
+        partial[2 * blockIdx.x + 1] = rw[0];
+        __threadfence();
+        unsigned tk = __hip_atomic_fetch_add(&info->ticket2, 1u, __ATOMIC_ACQ_REL,
+                                             __HIP_MEMORY_SCOPE_AGENT);
+        last = (tk == gridDim.x - 1);
+    }
+    __syncthreads();
+    if (!last) return;
+    __threadfence();
+    if (threadIdx.x == 0) {
+        double K = 0.0, W = 0.0;
+        for (unsigned b = 0; b < gridDim.x; ++b) {
+            K += __builtin_nontemporal_load(&partial[2 * b]);
+            W += __builtin_nontemporal_load(&partial[2 * b + 1]);
+        }
+        out[0] = K;
+        out[1] = 0.5 * W;
+        __hip_atomic_store(&info->ticket2, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+}
+
+static bool pow2(double d) {
+    int e;
+    return d > 0 && std::isfinite(d) && std::frexp(d, &e) == 0.5;
+}
+
+}  // namespace nb
+
+using namespace nb;
+
+extern "C" {
+
+int nbody_predict(nbody_ctx *ctx, int64_t n, double t_target, const double *t, const double *x,
+                  const double *v, const double *a, const double *k, double *xp, double *vp) {
+    if (!ctx) return NBODY_E_INVAL;
+    if (n < 0 || !std::isfinite(t_target)) return fail(ctx, NBODY_E_INVAL, "nbody_predict: bad args");
+    if (n == 0) return NBODY_OK;
+    if (!t || !x || !v || !a || !k || !xp || !vp)
+        return fail(ctx, NBODY_E_INVAL, "nbody_predict: null array");
+    NB_TRY(activate(ctx));
+    predict_kernel<<<grid_for(n, 256, 16 * ctx->cus), 256, 0, ctx->stream>>>(
+        n, t_target, nullptr, t, x, v, a, k, xp, vp, nullptr, nullptr, 0);
+    return hip_check(ctx, hipGetLastError(), "predict_kernel");
+}
+
+int nbody_schedule(nbody_ctx *ctx, int64_t n, const double *t, const double *dt,
+                   int32_t *active_idx, int64_t *n_i_out, double *t_next_out) {
+    if (!ctx) return NBODY_E_INVAL;
+    if (n < 1 || n > 0x7fffffffLL || !t || !dt || !active_idx || !n_i_out || !t_next_out)
+        return fail(ctx, NBODY_E_INVAL, "nbody_schedule: bad args");
+    NB_TRY(activate(ctx));
+    set_info_kernel<<<1, 64, 0, ctx->stream>>>(ctx->info, INFINITY, 0);
+    return launch_schedule(ctx, n, t, dt, active_idx, 0, n_i_out, t_next_out);
+}
+
+int nbody_correct(nbody_ctx *ctx, int64_t n, int64_t n_i, const int32_t *active_idx,
+                  const double *xp, const double *vp, const double *acc_new,
+                  const double *jerk_new, double eta, double dt_max, double dt_min,
+                  int fixed_dt, double *t, double *dt, double *x, double *v, double *a,
+                  double *k) {
+    if (!ctx) return NBODY_E_INVAL;
+    if (n < 1 || n_i < 0 || (active_idx == nullptr && n_i > n) || !(dt_min > 0) ||
+        !(dt_max >= dt_min) || !(eta > 0 || fixed_dt))
+        return fail(ctx, NBODY_E_INVAL, "nbody_correct: bad args");
+    if (n_i == 0) return NBODY_OK;
+    if (!xp || !vp || !acc_new || !jerk_new || !t || !dt || !x || !v || !a || !k)
+        return fail(ctx, NBODY_E_INVAL, "nbody_correct: null array");
+    NB_TRY(activate(ctx));
+    correct_kernel<<<grid_for(n_i, 256, 16 * ctx->cus), 256, 0, ctx->stream>>>(
+        n, n_i, nullptr, ctx->info, active_idx, xp, vp, acc_new, jerk_new, n_i, eta, dt_max,
+        dt_min, fixed_dt, t, dt, x, v, a, k);
+    return hip_check(ctx, hipGetLastError(), "correct_kernel");
+}
+
+int nbody_initial_dt(nbody_ctx *ctx, int64_t n, double t0, const double *a, const double *k,
+                     double eta_s, double dt_max, double dt_min, double *dt) {
+    if (!ctx) return NBODY_E_INVAL;
+    if (n < 0 || !pow2(dt_max) || !(dt_min > 0) || !(dt_max >= dt_min) || !(eta_s > 0) ||
+        !std::isfinite(t0))
+        return fail(ctx, NBODY_E_INVAL, "nbody_initial_dt: bad args");
+    if (n == 0) return NBODY_OK;
+    if (!a || !k || !dt) return fail(ctx, NBODY_E_INVAL, "nbody_initial_dt: null array");
+    NB_TRY(activate(ctx));
+    initial_dt_kernel<<<grid_for(n, 256, 16 * ctx->cus), 256, 0, ctx->stream>>>(
+        n, t0, a, k, eta_s, dt_max, dt_min, dt, ctx->info);
+    return hip_check(ctx, hipGetLastError(), "initial_dt_kernel");
+}
+
+int nbody_energy(nbody_ctx *ctx, int64_t n, const double *pos, const double *vel,
+                 const double *mass, double eps2, double *out) {
+    if (!ctx) return NBODY_E_INVAL;
+    if (n < 1 || n > 0x7fffffffLL || !(eps2 >= 0) || std::isinf(eps2) || !pos || !vel ||
+        !mass || !out)
+        return fail(ctx, NBODY_E_INVAL, "nbody_energy: bad args");
+    NB_TRY(activate(ctx));
+    const unsigned g = grid_for(n, 256, 1 << 30);
+    NB_TRY(ensure(ctx, &ctx->part, &ctx->part_bytes, (size_t)g * 2 * sizeof(double)));
+    energy_kernel<<<g, 256, 0, ctx->stream>>>(n, pos, vel, mass, eps2, (double *)ctx->part,
+                                              ctx->info, out);
+    return hip_check(ctx, hipGetLastError(), "energy_kernel");
+}
+
+static int check_system(nbody_ctx *ctx, const nbody_system *s) {
+    if (!s || s->n < 1 || s->n > 0x7fffffffLL)
+        return fail(ctx, NBODY_E_INVAL, "system: bad size");
+    if (!s->t || !s->dt || !s->x || !s->v || !s->a || !s->k || !s->m)
+        return fail(ctx, NBODY_E_INVAL, "system: null array");
+    if (!(s->eps2 >= 0) || std::isinf(s->eps2) || !(s->eta > 0) || !(s->eta_s > 0) ||
+        !pow2(s->dt_max) || !(s->dt_min > 0) || !(s->dt_max >= s->dt_min))
+        return fail(ctx, NBODY_E_INVAL, "system: bad parameters");
+    if (s->flags & ~(NBODY_ACC_DS | NBODY_FIXED_DT))
+        return fail(ctx, NBODY_E_INVAL, "system: unknown flags");
+    return NBODY_OK;
+}
+
+int nbody_init(nbody_ctx *ctx, const nbody_system *s, double t0) {
+    if (!ctx) return NBODY_E_INVAL;
+    NB_TRY(check_system(ctx, s));
+    if (!std::isfinite(t0)) return fail(ctx, NBODY_E_INVAL, "nbody_init: bad t0");
+    NB_TRY(activate(ctx));
+    const int64_t n = s->n;
+    fill_kernel<<<grid_for(n, 256, 4 * ctx->cus), 256, 0, ctx->stream>>>(n, t0, s->t);
+    NB_TRY(hip_check(ctx, hipGetLastError(), "fill_kernel"));
+    NB_TRY(ensure(ctx, &ctx->jrec, &ctx->jrec_bytes, (size_t)n * sizeof(JRec)));
+    ForceCall c;
+    c.shape = pick_shape(ctx, n, n);
+    NB_TRY(launch_pack(ctx, c.shape.rep, n, s->x, s->v, s->m, (JRec *)ctx->jrec));
+    c.jrec = (const JRec *)ctx->jrec;
+    c.n_j = n;
+    c.pos = s->x;
+    c.vel = s->v;
+    c.n_i = n;
+    c.eps2 = s->eps2;
+    c.acc = s->a;
+    c.jerk = s->k;
+    c.out_stride = n;
+    c.ds = (s->flags & NBODY_ACC_DS) != 0;
+    NB_TRY(launch_force(ctx, c));
+    if (s->flags & NBODY_FIXED_DT) {
+        fill_kernel<<<grid_for(n, 256, 4 * ctx->cus), 256, 0, ctx->stream>>>(n, s->dt_max, s->dt);
+        return hip_check(ctx, hipGetLastError(), "fill_kernel");
+    }
+    initial_dt_kernel<<<grid_for(n, 256, 16 * ctx->cus), 256, 0, ctx->stream>>>(
+        n, t0, s->a, s->k, s->eta_s, s->dt_max, s->dt_min, s->dt, ctx->info);
+    return hip_check(ctx, hipGetLastError(), "initial_dt_kernel");
+}
+
+int nbody_blockstep(nbody_ctx *ctx, const nbody_system *s, int64_t max_steps, double t_end,
+                    int64_t *steps_done, int64_t *interactions) {
+    if (!ctx) return NBODY_E_INVAL;
+    NB_TRY(check_system(ctx, s));
+    if (max_steps < 0 || std::isnan(t_end)) return fail(ctx, NBODY_E_INVAL, "nbody_blockstep: bad args");
+    if (steps_done) *steps_done = 0;
+    if (interactions) *interactions = 0;
+    NB_TRY(activate(ctx));
+    const int64_t n = s->n;
+    // step buffers: xp, vp, acc_new, jerk_new (3n each) + active (n int32)
+    const size_t vec = (size_t)3 * n * sizeof(double);
+    NB_TRY(ensure(ctx, &ctx->bs, &ctx->bs_bytes, 4 * vec + (size_t)n * sizeof(int32_t)));
+    NB_TRY(ensure(ctx, &ctx->jrec, &ctx->jrec_bytes, (size_t)n * sizeof(JRec)));
+    double *xp = (double *)ctx->bs;
+    double *vp = (double *)((char *)ctx->bs + vec);
+    double *an = (double *)((char *)ctx->bs + 2 * vec);
+    double *kn = (double *)((char *)ctx->bs + 3 * vec);
+    int32_t *act = (int32_t *)((char *)ctx->bs + 4 * vec);
+    JRec *jr = (JRec *)ctx->jrec;
+
+    set_info_kernel<<<1, 64, 0, ctx->stream>>>(ctx->info, t_end, 1);
+    NB_TRY(hip_check(ctx, hipGetLastError(), "set_info"));
+
+    ForceCall c;
+    c.shape = dynamic_shape(ctx, n);
+    c.jrec = jr;
+    c.n_j = n;
+    c.pos = xp;
+    c.vel = vp;
+    c.active = act;
+    c.n_i_dev = &ctx->info->n_i;
+    c.n_i_cap = n;
+    c.eps2 = s->eps2;
+    c.acc = an;
+    c.jerk = kn;
+    c.pot = nullptr;
+    c.out_stride = n;
+    c.ds = (s->flags & NBODY_ACC_DS) != 0;
+
+    const unsigned gp = grid_for(n, 256, 16 * ctx->cus);
+    int64_t enq = 0, chunk = 4;
+    while (enq < max_steps) {
+        int64_t todo = max_steps - enq < chunk ? max_steps - enq : chunk;
+        for (int64_t q = 0; q < todo; ++q) {
+            NB_TRY(launch_schedule(ctx, n, s->t, s->dt, act, 1, nullptr, nullptr));
+            predict_kernel<<<gp, 256, 0, ctx->stream>>>(n, 0.0, ctx->info, s->t, s->x, s->v,
+                                                        s->a, s->k, xp, vp, s->m, jr,
+                                                        c.shape.rep);
+            NB_TRY(hip_check(ctx, hipGetLastError(), "predict_kernel"));
+            NB_TRY(launch_force(ctx, c));
+            correct_kernel<<<gp, 256, 0, ctx->stream>>>(
+                n, 0, ctx->info, ctx->info, act, xp, vp, an, kn, n, s->eta, s->dt_max, s->dt_min,
+                (s->flags & NBODY_FIXED_DT) ? 1 : 0, s->t, s->dt, s->x, s->v, s->a, s->k);
+            NB_TRY(hip_check(ctx, hipGetLastError(), "correct_kernel"));
+        }
+        enq += todo;
+        NB_TRY(hip_check(ctx, hipMemcpyAsync(ctx->info_host, ctx->info, sizeof(StepInfo),
+                                             hipMemcpyDeviceToHost, ctx->stream),
+                         "info read"));
+        NB_TRY(hip_check(ctx, hipStreamSynchronize(ctx->stream), "sync"));
+        if (ctx->prof.on) prof_resolve(ctx);
+        if (ctx->info_host->done || ctx->info_host->status) break;
+        if (chunk < 64) chunk *= 2;
+    }
+    if (steps_done) *steps_done = ctx->info_host->steps;
+    if (interactions) *interactions = ctx->info_host->interactions;
+    if (ctx->info_host->status) return nbody_sync_status(ctx);
+    return NBODY_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,63 @@
+"""The C-ABI library: built, loadable without a GPU, exporting every entry
+point include/nbody.h declares, and the Python binding declaring exactly
+those entry points.  No compute calls (there may be no GPU here)."""
+import ctypes
+import os
+import re
+import subprocess
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "nbody.h")
+
+
+def declared():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(nbody_[a-z_0-9]+)\s*\(", text)))
+
+
+def test_header_declares_entry_points():
+    names = declared()
+    for must in ("nbody_force", "nbody_predict", "nbody_correct", "nbody_blockstep",
+                 "nbody_schedule", "nbody_energy", "nbody_create", "nbody_destroy"):
+        assert must in names
+
+
+def test_library_exports_every_declared_symbol():
+    import paper_cs_0702135_amd._lib as L
+    if not os.path.exists(L.LIB_PATH):
+        pytest.fail("libnbody.so not built: run python -m paper_cs_0702135_amd.build")
+    lib = ctypes.CDLL(L.LIB_PATH)
+    missing = [n for n in declared() if not hasattr(lib, n)]
+    assert not missing, missing
+    out = subprocess.run(["nm", "-D", "--defined-only", L.LIB_PATH], capture_output=True,
+                         text=True).stdout
+    exported = set(re.findall(r"\bT (nbody_[a-z_0-9]+)$", out, flags=re.M))
+    assert set(declared()) <= exported
+
+
+def test_binding_covers_exactly_the_header():
+    import paper_cs_0702135_amd._lib as L
+    assert sorted(L.SIGNATURES) == declared()
+    lib = L.load()
+    assert lib.nbody_version() >= 10000
+
+
+def test_struct_layouts_match_header():
+    import paper_cs_0702135_amd._lib as L
+    # nbody_system: int64 n, 7 pointers, 5 doubles, uint32 flags (+ padding)
+    assert ctypes.sizeof(L.NBodySystem) == 8 + 7 * 8 + 5 * 8 + 8
+    assert ctypes.sizeof(L.NBodyForceConfig) == 6 * 4
+
+
+def test_create_without_gpu_reports_device_error():
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is present")
+    import paper_cs_0702135_amd._lib as L
+    lib = L.load()
+    h = ctypes.c_void_p()
+    assert lib.nbody_create(ctypes.byref(h), 0, None) == L.NBODY_E_DEVICE
+    assert lib.nbody_last_error(None) == b"null context"

@@ -1,0 +1,60 @@
+"""Pair-sum accuracy at N = 2^20 (Plummer, eps = 1/4096) on sampled particles.
+
+The GPU evaluates the whole active block in the same launch configuration
+the benchmark times; the oracle evaluates 4096 sampled particles of it (one
+by one over all 2^20 j).  Gates: float32 tile sums p99 <= 1e-5; the
+compensated sums must not be worse than the float32 sums and stay within
+the float32 pair-arithmetic floor (p99 <= 1e-6).
+"""
+import numpy as np
+import pytest
+
+from tests.gpu_util import dev, host, need_gpu, rel_vec_err, say
+from workloads.plummer import CONFIGS, plummer
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def big():
+    cfg = CONFIGS["plummer1m"]
+    pos, vel, m = plummer(cfg.n, cfg.seed)
+    return cfg, pos, vel, m
+
+
+@pytest.mark.parametrize("n_i", [1024, 16384, 262144, 1 << 20])
+def test_sampled_accuracy(orc, big, n_i):
+    need_gpu()
+    import paper_cs_0702135_amd as nb
+    import torch
+    cfg, pos, vel, m = big
+    n = cfg.n
+    rng = np.random.default_rng(cfg.seed + n_i)
+    sample_sz = min(cfg.extra["n_sample"], n_i)
+    sample = np.sort(rng.choice(n, size=sample_sz, replace=False)).astype(np.int32)
+    if n_i == n:
+        act = None
+        slots = sample
+    else:
+        rest = np.setdiff1d(np.arange(n), sample)
+        act = np.sort(np.concatenate([sample, rng.choice(rest, n_i - sample_sz, replace=False)]))
+        act = act.astype(np.int32)
+        slots = np.searchsorted(act, sample)
+    ref = orc.force(pos, vel, m, cfg.eps2, active=sample)
+    P, V, M = dev(pos), dev(vel), dev(m)
+    A = None if act is None else dev(act, torch.int32)
+    errs = {}
+    for mode in ("fp32", "ds"):
+        acc, jerk, pot = nb.force(P, V, M, cfg.eps2, A, mode)
+        acc, jerk, pot = host(acc)[:, slots], host(jerk)[:, slots], host(pot)[slots]
+        ea = rel_vec_err(acc, ref[0])
+        ej = rel_vec_err(jerk, ref[1])
+        ep = np.abs(pot - ref[2]) / np.abs(ref[2])
+        glob = np.sqrt(((acc - ref[0]) ** 2).sum() / (ref[0] ** 2).sum())
+        errs[mode] = (np.percentile(ea, 99), glob)
+        say("N=2^20 n_i=%d %s: acc p50 %.2e p99 %.2e max %.2e global %.2e | jerk p50 %.2e p99 %.2e"
+            " | pot p99 %.2e" % (n_i, mode, np.median(ea), np.percentile(ea, 99), ea.max(), glob,
+                                 np.median(ej), np.percentile(ej, 99), np.percentile(ep, 99)))
+    assert errs["fp32"][0] <= 1e-5
+    assert errs["ds"][0] <= 1e-6
+    assert errs["ds"][1] <= errs["fp32"][1] * 1.05

@@ -1,0 +1,158 @@
+"""GPU parity of the float64 integrator kernels and the block-step driver.
+
+Predictor, corrector, scheduler, initial steps and energy run in float64 on
+the GPU and are compared with the oracle on identical inputs: bitwise for
+the scheduler and the step sizes (integer/decision outputs), within a few
+float64 ulps for positions and velocities.  The block-step driver is
+compared step by step against the oracle started from the GPU's own state,
+and over a whole run by its energy conservation.
+"""
+import numpy as np
+import pytest
+
+from tests.gpu_util import dev, host, need_gpu, rel_vec_err, say
+from workloads.plummer import CONFIGS, plummer
+
+pytestmark = pytest.mark.gpu
+
+
+def _rand_state(n, seed):
+    rng = np.random.default_rng(seed)
+    x, v, a, k = (rng.normal(size=(3, n)) for _ in range(4))
+    e = rng.integers(3, 12, n)
+    dt = 2.0 ** -e
+    t = np.floor(rng.uniform(0, 1, n) / dt) * dt
+    return t, dt, x, v, a, k
+
+
+def test_predictor_matches_oracle(orc):
+    need_gpu()
+    import paper_cs_0702135_amd as nb
+    t, dt, x, v, a, k = _rand_state(5001, 1)
+    tn = float((t + dt).min())
+    xp, vp = nb.predict(tn, dev(t), dev(x), dev(v), dev(a), dev(k))
+    rx, rv = orc.predict(tn, t, x, v, a, k)
+    # same operations in the same order, no contraction: identical results
+    np.testing.assert_array_equal(host(xp), rx)
+    np.testing.assert_array_equal(host(vp), rv)
+
+
+@pytest.mark.parametrize("n", [1, 7, 1000, 300001])
+def test_scheduler_matches_oracle(orc, n):
+    need_gpu()
+    import paper_cs_0702135_amd as nb
+    t, dt, *_ = _rand_state(n, 2 + n)
+    act, tn = nb.schedule(dev(t), dev(dt))
+    rtn, ract = orc.schedule(t, dt)
+    assert tn == rtn
+    np.testing.assert_array_equal(host(act), ract)
+
+
+def test_initial_dt_matches_oracle(orc):
+    need_gpu()
+    import paper_cs_0702135_amd as nb
+    rng = np.random.default_rng(3)
+    a = rng.normal(size=(3, 4000))
+    k = rng.normal(size=(3, 4000)) * 10 ** rng.uniform(-2, 3, 4000)
+    for t0 in (0.0, 0.375):
+        dt = nb.initial_dt(t0, dev(a), dev(k), 0.01, 0.125, 2.0 ** -40)
+        rdt, rc = orc.initial_dt(t0, a, k, 0.01, 0.125, 2.0 ** -40)
+        np.testing.assert_array_equal(host(dt), rdt)
+
+
+def test_corrector_matches_oracle(orc):
+    # identical inputs, including the new force: x, v within a few ulps,
+    # step decisions identical
+    need_gpu()
+    import paper_cs_0702135_amd as nb
+    import torch
+    pos, vel, m = plummer(2048, 4)
+    eps2 = (1 / 256) ** 2
+    s = orc.init_state(pos, vel, m, eps2)
+    for _ in range(30):  # get a realistic mix of steps and times
+        orc.blockstep(s)
+    tn, act = orc.schedule(s.t, s.dt)
+    xp, vp = orc.predict(tn, s.t, s.x, s.v, s.a, s.k)
+    an, kn, _ = orc.force(xp, vp, m, eps2, active=act)
+    ref = s.copy()
+    rc = orc.correct(act, xp, vp, an, kn, s.eta, s.dt_max, s.dt_min, ref.t, ref.dt, ref.x,
+                     ref.v, ref.a, ref.k)
+    assert rc == 0
+    T, DT, X, V, A, K = (dev(q) for q in (s.t, s.dt, s.x, s.v, s.a, s.k))
+    nb.correct(dev(act, torch.int32), dev(xp), dev(vp), dev(an), dev(kn), s.eta, s.dt_max,
+               s.dt_min, T, DT, X, V, A, K)
+    nb.context().sync_status()
+    np.testing.assert_array_equal(host(T), ref.t)
+    np.testing.assert_array_equal(host(DT), ref.dt)
+    np.testing.assert_allclose(host(X), ref.x, rtol=4e-16, atol=4e-16)
+    np.testing.assert_allclose(host(V), ref.v, rtol=4e-16, atol=4e-16)
+    np.testing.assert_array_equal(host(A), ref.a)
+
+
+@pytest.mark.parametrize("n", [2, 333, 4096])
+def test_energy_matches_oracle(orc, n):
+    need_gpu()
+    import paper_cs_0702135_amd as nb
+    pos, vel, m = plummer(n, 5 + n)
+    eps2 = 1e-4
+    K, W = nb.energy(dev(pos), dev(vel), dev(m), eps2)
+    rK, rW = orc.energy(pos, vel, m, eps2)
+    assert abs(K - rK) <= 1e-14 * abs(rK)
+    assert abs(W - rW) <= 1e-13 * abs(rW)
+
+
+def test_blockstep_steps_match_oracle_from_same_state(orc):
+    # Each GPU block step is compared with one oracle step taken from the
+    # GPU's own state before the step: same block, same new time, positions
+    # within the float32-force error carried through the corrector.
+    need_gpu()
+    import paper_cs_0702135_amd as nb
+    cfg = CONFIGS["plummer1k"]
+    pos, vel, m = plummer(cfg.n, cfg.seed)
+    sysg = nb.System(dev(pos), dev(vel), dev(m), cfg.eps2, eta=cfg.eta, dt_max=cfg.dt_max)
+    flips = 0
+    worst = 0.0
+    for step in range(60):
+        st = orc.State(host(sysg.t), host(sysg.dt), host(sysg.x), host(sysg.v), host(sysg.a),
+                       host(sysg.k), m, cfg.eps2, cfg.eta, 0.01, cfg.dt_max, 2.0 ** -40)
+        n_i, tn, act = orc.blockstep(st)
+        assert sysg.step(1) == 1
+        t_gpu = host(sysg.t)
+        np.testing.assert_array_equal(t_gpu, st.t)  # same block, same new time
+        ex = np.abs(host(sysg.x)[:, act] - st.x[:, act]).max()
+        worst = max(worst, ex)
+        flips += int((host(sysg.dt) != st.dt).sum())
+    say("max |dx| over 60 steps %.2e, step-size flips %d" % (worst, flips))
+    assert worst < 1e-9
+    assert flips <= 2
+
+
+@pytest.mark.parametrize("mode", ["fp32", "ds"])
+def test_blockstep_energy_drift(orc, mode):
+    # Plummer N=1024, eps=1/256, eta=0.02, to t=1/4: relative energy drift
+    # per time unit below 1e-6, and the run's block statistics close to the
+    # oracle's own run
+    need_gpu()
+    import paper_cs_0702135_amd as nb
+    cfg = CONFIGS["plummer1k"]
+    pos, vel, m = plummer(cfg.n, cfg.seed)
+    sysg = nb.System(dev(pos), dev(vel), dev(m), cfg.eps2, eta=cfg.eta, dt_max=cfg.dt_max,
+                     mode=mode)
+    e0 = sysg.energy()
+    steps = sysg.run(cfg.t_end)
+    e1 = sysg.energy()
+    assert np.all(host(sysg.t) == cfg.t_end)
+    drift = abs((e1 - e0) / e0) / cfg.t_end
+    s = orc.init_state(pos, vel, m, cfg.eps2)
+    rsteps, _ = orc.integrate(s, cfg.t_end)
+    say("mode %s: GPU steps %d (oracle %d), drift/unit %.2e" % (mode, steps, rsteps, drift))
+    assert drift < 1e-6
+    assert abs(steps - rsteps) <= 0.05 * rsteps
+
+
+def test_system_rejects_bad_parameters():
+    need_gpu()
+    import paper_cs_0702135_amd as nb
+    pos, vel, m = plummer(64, 1)
+    with pytest.raises(nb.NBodyError):
+        nb.System(dev(pos), dev(vel), dev(m), 1e-4, dt_max=0.1)  # not a power of two
