@@ -190,6 +190,50 @@ int nbody_blockstep(nbody_ctx *ctx, const nbody_system *sys,
                     int64_t max_steps, double t_end, int64_t *steps_done,
                     int64_t *interactions);
 
+/* ---- adjoint (not in the paper: the transpose of the pair sums above) ----
+ * For the full set (every particle is both i and j, n_i = n_j = n) and
+ * cotangents abar, kbar, pbar of acc, jerk, pot, writes
+ *   pos_bar = dL/dx,  vel_bar = dL/dv,  mass_bar = dL/dm
+ * of L = sum_i abar_i.acc_i + kbar_i.jerk_i + pbar_i pot_i.  Per pair (i, j),
+ * with r, w, S as for nbody_force, q = r.w, al = S^(-3/2), be = S^(-5/2),
+ * ga = S^(-7/2):
+ *   g_r = m_j [al abar_i - 3 q be kbar_i - 3 be (kbar_i.r) w
+ *              + (pbar_i al - 3 be (abar_i.r + kbar_i.w) + 15 q ga (kbar_i.r)) r]
+ *   g_v = m_j [al kbar_i - 3 be (kbar_i.r) r]
+ *   g_m = al (abar_i.r + kbar_i.w) - 3 q be (kbar_i.r) - pbar_i S^(-1/2)
+ * contribute pos_bar_j += g_r, pos_bar_i -= g_r, vel_bar_j += g_v,
+ * vel_bar_i -= g_v, mass_bar_j += g_m.  float32 pair arithmetic on float64
+ * relative coordinates, accumulation as selected by flags.
+ *   pos, vel, acc_bar, jerk_bar, pos_bar, vel_bar : float64[3n]
+ *   mass, pot_bar (may be NULL = zero), mass_bar  : float64[n]
+ * Outputs are overwritten. */
+int nbody_force_adjoint(nbody_ctx *ctx, int64_t n, const double *pos,
+                        const double *vel, const double *mass, double eps2,
+                        const double *acc_bar, const double *jerk_bar,
+                        const double *pot_bar, double *pos_bar, double *vel_bar,
+                        double *mass_bar, uint32_t flags);
+
+/* Transpose of the predictor for one shared step h (Section 2 predictor is
+ * linear in x, v, a, k), ACCUMULATED into the outputs:
+ *   x_bar += xp_bar;  v_bar += h xp_bar + vp_bar;
+ *   a_bar += (h^2/2) xp_bar + h vp_bar;  k_bar += (h^3/6) xp_bar + (h^2/2) vp_bar.
+ * All arrays float64[3n]. */
+int nbody_predict_adjoint(nbody_ctx *ctx, int64_t n, double h, const double *xp_bar,
+                          const double *vp_bar, double *x_bar, double *v_bar,
+                          double *a_bar, double *k_bar);
+
+/* Transpose of the corrector for one shared step h (Section 2 corrector,
+ * linear in xp, vp, a0, k0, a1, k1 once a2, a3 are expanded:
+ *   x1 = xp - (3/20) h^2 (a0 - a1) - h^3 (7 k0/60 + k1/30),
+ *   v1 = vp - (h/2) (a0 - a1) - h^2 (5 k0/12 + k1/12)),
+ * ACCUMULATED into xp_bar, vp_bar, a0_bar, k0_bar, a1_bar, k1_bar.  The
+ * step's outputs a <- a1, k <- k1 pass their cotangents through unchanged
+ * (the caller adds them to a1_bar, k1_bar).  All arrays float64[3n]. */
+int nbody_correct_adjoint(nbody_ctx *ctx, int64_t n, double h, const double *x1_bar,
+                          const double *v1_bar, double *xp_bar, double *vp_bar,
+                          double *a0_bar, double *k0_bar, double *a1_bar,
+                          double *k1_bar);
+
 /* ---- launch shape of the pair kernels (autotuning) ----------------------
  * The pair kernels are compiled in several shapes; a context keeps a table
  * of which shape to use for which active-block size.  Without entries a

@@ -63,6 +63,9 @@ SIGNATURES = {
     "nbody_init": (INT, [P, ctypes.POINTER(NBodySystem), D]),
     "nbody_blockstep": (INT, [P, ctypes.POINTER(NBodySystem), I64, D,
                               ctypes.POINTER(I64), ctypes.POINTER(I64)]),
+    "nbody_force_adjoint": (INT, [P, I64, P, P, P, D, P, P, P, P, P, P, U32]),
+    "nbody_predict_adjoint": (INT, [P, I64, D, P, P, P, P, P, P]),
+    "nbody_correct_adjoint": (INT, [P, I64, D, P, P, P, P, P, P, P, P]),
     "nbody_tune_set": (INT, [P, I64, I64, ctypes.POINTER(NBodyForceConfig)]),
     "nbody_tune_clear": (INT, [P]),
     "nbody_profile": (INT, [P, INT, ctypes.POINTER(D), ctypes.POINTER(D),

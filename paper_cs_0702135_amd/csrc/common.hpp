@@ -154,6 +154,8 @@ struct nbody_ctx {
     size_t part_bytes = 0;
     void *work = nullptr;  // scheduler / reduction scratch
     size_t work_bytes = 0;
+    void *adj = nullptr;  // adjoint source records
+    size_t adj_bytes = 0;
     nb::StepInfo *info = nullptr;  // device
     nb::StepInfo *info_host = nullptr;  // pinned host mirror
     // block-step buffers

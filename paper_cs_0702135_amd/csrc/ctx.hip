@@ -149,7 +149,7 @@ int nbody_destroy(nbody_ctx *ctx) {
     if (!ctx) return NBODY_OK;
     (void)hipSetDevice(ctx->device);
     (void)hipStreamSynchronize(ctx->stream);
-    void *bufs[] = {ctx->jrec, ctx->part, ctx->work, ctx->bs, ctx->info};
+    void *bufs[] = {ctx->jrec, ctx->part, ctx->work, ctx->bs, ctx->adj, ctx->info};
     for (void *b : bufs)
         if (b) (void)hipFree(b);
     if (ctx->info_host) (void)hipHostFree(ctx->info_host);

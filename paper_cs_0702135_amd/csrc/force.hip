@@ -23,6 +23,7 @@
 #include <cmath>
 
 #include "common.hpp"
+#include "pairs.hpp"
 
 namespace nb {
 
@@ -50,8 +51,6 @@ int launch_pack(nbody_ctx *ctx, int rep, int64_t n, const double *pos, const dou
 }
 
 // ---- record forms: scalar-path loads and relative coordinates -------------
-#define CONSTP(T) const __attribute__((address_space(4))) T *
-
 template <int REP>
 struct Form;
 
@@ -148,60 +147,6 @@ struct Form<REP_F64V> {
         dw = r.w - s.w;
     }
 };
-
-struct KArgs {
-    const JRec *__restrict__ jrec;
-    const double *__restrict__ pos;
-    const double *__restrict__ vel;
-    const int32_t *__restrict__ active;
-    const int64_t *__restrict__ n_i_dev;
-    double *__restrict__ acc;
-    double *__restrict__ jerk;
-    double *__restrict__ pot;
-    double *__restrict__ part;
-    int32_t *status;  // latched error bits (an active index out of range)
-    int64_t n_i;
-    int64_t out_stride;  // <= 0: use n_i
-    int32_t n_j;
-    float eps2;
-    int32_t tile;
-    int32_t min_j_wave;
-    int32_t target_groups;
-    int32_t max_splits;
-};
-
-// Number of workgroups that share one i-block's j range.
-__host__ __device__ inline int64_t choose_splits(int64_t n_i, int64_t n_j, int it, int waves,
-                                                 int min_j_wave, int target_groups,
-                                                 int max_splits) {
-    int64_t nb = (n_i + 64 * it - 1) / (64 * it);
-    if (nb < 1) nb = 1;
-    int64_t s = (target_groups + nb - 1) / nb;
-    int64_t smax = n_j / ((int64_t)waves * min_j_wave);
-    if (smax > max_splits) smax = max_splits;
-    if (s > smax) s = smax;
-    if (s < 1) s = 1;
-    return s;
-}
-
-__device__ __forceinline__ void two_sum_acc(float &hi, float &lo, float x) {
-    const float s = hi + x;
-    const float bp = s - hi;
-    const float e = (hi - (s - bp)) + (x - bp);
-    hi = s;
-    lo += e;
-}
-
-__device__ __forceinline__ int wave_min(int v) {
-#pragma unroll
-    for (int o = 32; o >= 1; o >>= 1) v = min(v, __shfl_xor(v, o, 64));
-    return v;
-}
-__device__ __forceinline__ int wave_max(int v) {
-#pragma unroll
-    for (int o = 32; o >= 1; o >>= 1) v = max(v, __shfl_xor(v, o, 64));
-    return v;
-}
 
 template <int REP, int IT, int W, bool DS>
 __global__ __launch_bounds__(64 * W) void force_kernel(const KArgs a) {
@@ -399,7 +344,6 @@ __global__ __launch_bounds__(64 * W) void force_kernel(const KArgs a) {
 // lanes of a wave take 64 consecutive outputs, the RW waves of a workgroup
 // take contiguous quarters of the splits, and the wave sums are combined in
 // wave order through LDS.
-constexpr int RW = 8;
 __global__ __launch_bounds__(64 * RW) void reduce_parts_kernel(const KArgs a, int it, int waves) {
     __shared__ double red[RW][64];
     const int64_t n_i = a.n_i_dev ? *a.n_i_dev : a.n_i;
@@ -435,6 +379,15 @@ __global__ __launch_bounds__(64 * RW) void reduce_parts_kernel(const KArgs a, in
         }
         __syncthreads();
     }
+}
+
+int launch_reduce_parts(nbody_ctx *ctx, const KArgs &a, int it, int waves, int64_t n_i_max) {
+    int64_t blocks = (7 * n_i_max + 63) / 64;
+    if (blocks > 16 * (int64_t)ctx->cus) blocks = 16 * (int64_t)ctx->cus;
+    if (blocks < 1) blocks = 1;
+    hipLaunchKernelGGL(reduce_parts_kernel, dim3((unsigned)blocks), dim3(64 * RW), 0, ctx->stream,
+                       a, it, waves);
+    return hip_check(ctx, hipGetLastError(), "reduce_parts_kernel");
 }
 
 typedef void (*force_fn)(const KArgs);
@@ -477,7 +430,6 @@ static force_fn pick_kernel(const ForceShape &s, bool ds) {
     }
 }
 
-static const int kMaxSplits = 1024;
 
 static ForceShape default_shape(const nbody_ctx *ctx) {
     ForceShape s;
@@ -573,13 +525,8 @@ int launch_force(nbody_ctx *ctx, const ForceCall &c) {
     NB_TRY(hip_check(ctx, hipGetLastError(), "force_kernel"));
     if (ctx->prof.on) prof_push(ctx, e0, prof_mark(ctx), 0);
     if (need_part > 0) {
-        int64_t blocks = (7 * n_i_max + 63) / 64;
-        if (blocks > 16 * (int64_t)ctx->cus) blocks = 16 * (int64_t)ctx->cus;
-        if (blocks < 1) blocks = 1;
         hipEvent_t r0 = ctx->prof.on ? prof_mark(ctx) : nullptr;
-        hipLaunchKernelGGL(reduce_parts_kernel, dim3((unsigned)blocks), dim3(64 * RW), 0,
-                           ctx->stream, a, sh.it, sh.waves);
-        NB_TRY(hip_check(ctx, hipGetLastError(), "reduce_parts_kernel"));
+        NB_TRY(launch_reduce_parts(ctx, a, sh.it, sh.waves, n_i_max));
         if (ctx->prof.on) prof_push(ctx, r0, prof_mark(ctx), 1);
     }
     return NBODY_OK;

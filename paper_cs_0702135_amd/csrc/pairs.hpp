@@ -1,0 +1,73 @@
+// Internal declarations shared by the pair kernels (sums and adjoint).
+#pragma once
+
+#include "common.hpp"
+
+namespace nb {
+
+// Pointer into the constant address space: wave-uniform loads through it
+// become scalar loads (SGPR results).
+#define CONSTP(T) const __attribute__((address_space(4))) T *
+
+constexpr int kMaxSplits = 1024;  // largest j split across workgroups
+constexpr int RW = 8;             // waves per group of the split reduction
+
+struct KArgs {
+    const JRec *__restrict__ jrec;
+    const double *__restrict__ pos;
+    const double *__restrict__ vel;
+    const int32_t *__restrict__ active;
+    const int64_t *__restrict__ n_i_dev;
+    double *__restrict__ acc;
+    double *__restrict__ jerk;
+    double *__restrict__ pot;
+    double *__restrict__ part;
+    int32_t *status;  // latched error bits (an active index out of range)
+    int64_t n_i;
+    int64_t out_stride;  // <= 0: use n_i
+    int32_t n_j;
+    float eps2;
+    int32_t tile;
+    int32_t min_j_wave;
+    int32_t target_groups;
+    int32_t max_splits;
+};
+
+// Number of workgroups that share one i-block's j range.
+__host__ __device__ inline int64_t choose_splits(int64_t n_i, int64_t n_j, int it, int waves,
+                                                 int min_j_wave, int target_groups,
+                                                 int max_splits) {
+    int64_t nb = (n_i + 64 * it - 1) / (64 * it);
+    if (nb < 1) nb = 1;
+    int64_t s = (target_groups + nb - 1) / nb;
+    int64_t smax = n_j / ((int64_t)waves * min_j_wave);
+    if (smax > max_splits) smax = max_splits;
+    if (s > smax) s = smax;
+    if (s < 1) s = 1;
+    return s;
+}
+
+__device__ __forceinline__ void two_sum_acc(float &hi, float &lo, float x) {
+    const float s = hi + x;
+    const float bp = s - hi;
+    const float e = (hi - (s - bp)) + (x - bp);
+    hi = s;
+    lo += e;
+}
+
+__device__ __forceinline__ int wave_min(int v) {
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) v = min(v, __shfl_xor(v, o, 64));
+    return v;
+}
+__device__ __forceinline__ int wave_max(int v) {
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) v = max(v, __shfl_xor(v, o, 64));
+    return v;
+}
+
+// Adds the S float64 partial sums [S][7][n_i] of the 7 outputs in split
+// order and writes acc (q < 3), jerk (q < 6) and pot (q = 6).
+int launch_reduce_parts(nbody_ctx *ctx, const KArgs &a, int it, int waves, int64_t n_i_max);
+
+}  // namespace nb
