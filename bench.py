@@ -35,7 +35,7 @@ HBM_PEAK_GBS = 8000.0
 def kernel_source_digest():
     import hashlib
     h = hashlib.sha256()
-    for f in ("force.hip", "pairs.hpp", "common.hpp"):
+    for f in ("force.hip", "pairs.hpp", "records.hpp"):
         with open(os.path.join(ROOT, "paper_cs_0702135_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()

@@ -59,6 +59,9 @@ extern "C" {
  * nbody_init), i.e. shared steps in which every block step advances all
  * particles; the step criterion is not evaluated. */
 #define NBODY_FIXED_DT 2u
+/* nbody_force_adjoint only: add into pos_bar, vel_bar, mass_bar instead of
+ * overwriting them. */
+#define NBODY_ADJ_ACCUMULATE 4u
 
 typedef struct nbody_ctx nbody_ctx;
 
@@ -190,6 +193,45 @@ int nbody_blockstep(nbody_ctx *ctx, const nbody_system *sys,
                     int64_t max_steps, double t_end, int64_t *steps_done,
                     int64_t *interactions);
 
+/* ---- batched ensemble ----------------------------------------------------
+ * Many independent clusters, each integrated with the block steps of
+ * nbody_blockstep (same predictor, pair sums, corrector and step rules),
+ * all in ONE persistent cooperative launch.  Cluster c is particles
+ * [offsets[c], offsets[c+1]) of the concatenated arrays, with its own eps2;
+ * clusters do not interact.  Every cluster is initialised at t = 0 (pair
+ * sums of all its particles, initial steps as nbody_initial_dt) and
+ * advanced until its next block would pass t_end (so all its particles end
+ * at t_end when t_end is a multiple of dt_max).  Synchronises.
+ *   offsets, eps2 : HOST arrays int64[n_clusters + 1] (offsets[0] = 0,
+ *                   strictly increasing) and float64[n_clusters].
+ *   t, dt, m      : device float64[n_total];  x, v, a, k : device
+ *                   float64[3 n_total] with component stride n_total
+ *                   (t, dt, a, k are outputs; x, v are advanced in place).
+ *   steps, interactions : HOST int64[n_clusters] outputs (may be NULL):
+ *                   block steps and sum of n_i * N per cluster.
+ * Returns NBODY_E_DEVICE if the launch could not be made co-resident or a
+ * team barrier timed out, else the latched step / non-finite status. */
+typedef struct nbody_ensemble {
+    int32_t n_clusters;
+    const int64_t *offsets;
+    const double *eps2;
+    double *t, *dt;
+    double *x, *v, *a, *k;
+    const double *m;
+    double eta, eta_s, dt_max, dt_min;
+    uint32_t flags; /* NBODY_ACC_FP32 or NBODY_ACC_DS */
+} nbody_ensemble;
+
+int nbody_ensemble_run(nbody_ctx *ctx, const nbody_ensemble *e, double t_end,
+                       int64_t *steps, int64_t *interactions);
+
+/* Launch shape of the ensemble: workgroups per CU in the persistent grid
+ * (1..8, capped by occupancy) and the largest team of workgroups one
+ * cluster may get (1..4096). */
+int nbody_ensemble_set(nbody_ctx *ctx, int32_t groups_per_cu, int32_t max_team);
+/* Grid size and number of teams of the last ensemble launch (HOST outputs). */
+int nbody_ensemble_info(nbody_ctx *ctx, int32_t *grid, int32_t *teams);
+
 /* ---- adjoint (not in the paper: the transpose of the pair sums above) ----
  * For the full set (every particle is both i and j, n_i = n_j = n) and
  * cotangents abar, kbar, pbar of acc, jerk, pot, writes
@@ -203,10 +245,11 @@ int nbody_blockstep(nbody_ctx *ctx, const nbody_system *sys,
  *   g_m = al (abar_i.r + kbar_i.w) - 3 q be (kbar_i.r) - pbar_i S^(-1/2)
  * contribute pos_bar_j += g_r, pos_bar_i -= g_r, vel_bar_j += g_v,
  * vel_bar_i -= g_v, mass_bar_j += g_m.  float32 pair arithmetic on float64
- * relative coordinates, accumulation as selected by flags.
+ * relative coordinates, accumulation as selected by flags (NBODY_ACC_*, and
+ * NBODY_ADJ_ACCUMULATE to add into the outputs).
  *   pos, vel, acc_bar, jerk_bar, pos_bar, vel_bar : float64[3n]
  *   mass, pot_bar (may be NULL = zero), mass_bar  : float64[n]
- * Outputs are overwritten. */
+ * Outputs are overwritten unless NBODY_ADJ_ACCUMULATE is set. */
 int nbody_force_adjoint(nbody_ctx *ctx, int64_t n, const double *pos,
                         const double *vel, const double *mass, double eps2,
                         const double *acc_bar, const double *jerk_bar,

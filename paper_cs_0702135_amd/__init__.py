@@ -25,6 +25,8 @@ __all__ = [
     "NBodyError", "Context", "context", "force", "predict", "schedule",
     "correct", "initial_dt", "energy", "System", "ACC_FP32", "ACC_DS",
     "ForceShape", "tune_set", "tune_clear", "tune_get", "profile",
+    "force_adjoint", "predict_adjoint", "correct_adjoint", "ensemble_run",
+    "ensemble_set", "ensemble_info",
 ]
 
 ACC_FP32 = L.NBODY_ACC_FP32
@@ -201,6 +203,103 @@ def energy(pos, vel, mass, eps2):
                                    _ptr(out)))
     K, W = out.tolist()
     return K, W
+
+
+def force_adjoint(pos, vel, mass, eps2, acc_bar, jerk_bar, pot_bar=None, mode="fp32", out=None):
+    """(pos_bar, vel_bar, mass_bar) of L = sum acc_bar.acc + jerk_bar.jerk + pot_bar.pot
+    for the full set of particles (nbody_force_adjoint).  With `out` given,
+    the gradients are added into those three tensors."""
+    n = mass.shape[0]
+    _vec(pos, n, "pos"), _vec(vel, n, "vel"), _sca(mass, n, "mass")
+    _vec(acc_bar, n, "acc_bar"), _vec(jerk_bar, n, "jerk_bar")
+    if pot_bar is not None:
+        _sca(pot_bar, n, "pot_bar")
+    flags = _mode(mode)
+    if out is None:
+        xb = torch.empty_like(pos)
+        vb = torch.empty_like(vel)
+        mb = torch.empty_like(mass)
+    else:
+        xb, vb, mb = out
+        _vec(xb, n, "pos_bar"), _vec(vb, n, "vel_bar"), _sca(mb, n, "mass_bar")
+        flags |= L.NBODY_ADJ_ACCUMULATE
+    ctx = context(pos.device)
+    ctx.check(ctx.lib.nbody_force_adjoint(ctx.bind(), n, _ptr(pos), _ptr(vel), _ptr(mass),
+                                          float(eps2), _ptr(acc_bar), _ptr(jerk_bar),
+                                          _ptr(pot_bar), _ptr(xb), _ptr(vb), _ptr(mb), flags))
+    return xb, vb, mb
+
+
+def predict_adjoint(h, xp_bar, vp_bar, x_bar, v_bar, a_bar, k_bar):
+    """Accumulate the predictor's transpose for a shared step h (in place)."""
+    n = xp_bar.shape[1]
+    for q, nm in ((xp_bar, "xp_bar"), (vp_bar, "vp_bar"), (x_bar, "x_bar"), (v_bar, "v_bar"),
+                  (a_bar, "a_bar"), (k_bar, "k_bar")):
+        _vec(q, n, nm)
+    ctx = context(xp_bar.device)
+    ctx.check(ctx.lib.nbody_predict_adjoint(ctx.bind(), n, float(h), _ptr(xp_bar), _ptr(vp_bar),
+                                            _ptr(x_bar), _ptr(v_bar), _ptr(a_bar), _ptr(k_bar)))
+
+
+def correct_adjoint(h, x1_bar, v1_bar, xp_bar, vp_bar, a0_bar, k0_bar, a1_bar, k1_bar):
+    """Accumulate the corrector's transpose for a shared step h (in place)."""
+    n = x1_bar.shape[1]
+    for q, nm in ((x1_bar, "x1_bar"), (v1_bar, "v1_bar"), (xp_bar, "xp_bar"),
+                  (vp_bar, "vp_bar"), (a0_bar, "a0_bar"), (k0_bar, "k0_bar"),
+                  (a1_bar, "a1_bar"), (k1_bar, "k1_bar")):
+        _vec(q, n, nm)
+    ctx = context(x1_bar.device)
+    ctx.check(ctx.lib.nbody_correct_adjoint(ctx.bind(), n, float(h), _ptr(x1_bar), _ptr(v1_bar),
+                                            _ptr(xp_bar), _ptr(vp_bar), _ptr(a0_bar),
+                                            _ptr(k0_bar), _ptr(a1_bar), _ptr(k1_bar)))
+
+
+def ensemble_run(pos, vel, mass, offsets, eps2, t_end, eta=0.02, eta_s=0.01, dt_max=0.0625,
+                 dt_min=2.0 ** -40, mode="fp32"):
+    """Integrate independent clusters (particles [offsets[c], offsets[c+1]) of
+    the concatenated (3, n) arrays, softening eps2[c]) from t = 0 to t_end in
+    one persistent launch (nbody_ensemble_run).
+
+    Returns a dict with the final t, dt, x, v, a, k tensors and host lists of
+    block steps and interactions per cluster.
+    """
+    import numpy as _np
+    n = mass.shape[0]
+    _vec(pos, n, "pos"), _vec(vel, n, "vel"), _sca(mass, n, "mass")
+    off = _np.ascontiguousarray(offsets, dtype=_np.int64)
+    e2 = _np.ascontiguousarray(eps2, dtype=_np.float64)
+    nc = off.shape[0] - 1
+    if nc < 1 or e2.shape[0] != nc or off[-1] != n:
+        raise ValueError("offsets must have n_clusters + 1 entries ending at n, eps2 n_clusters")
+    st = {"x": pos.clone(), "v": vel.clone(),
+          "t": torch.empty((n,), dtype=torch.float64, device=pos.device),
+          "dt": torch.empty((n,), dtype=torch.float64, device=pos.device),
+          "a": torch.empty_like(pos), "k": torch.empty_like(pos)}
+    e = L.NBodyEnsemble(nc, off.ctypes.data_as(ctypes.c_void_p), e2.ctypes.data_as(ctypes.c_void_p),
+                        st["t"].data_ptr(), st["dt"].data_ptr(), st["x"].data_ptr(),
+                        st["v"].data_ptr(), st["a"].data_ptr(), st["k"].data_ptr(),
+                        mass.data_ptr(), float(eta), float(eta_s), float(dt_max), float(dt_min),
+                        _mode(mode))
+    steps = (ctypes.c_int64 * nc)()
+    inter = (ctypes.c_int64 * nc)()
+    ctx = context(pos.device)
+    ctx.check(ctx.lib.nbody_ensemble_run(ctx.bind(), ctypes.byref(e), float(t_end), steps, inter))
+    st["steps"] = list(steps)
+    st["interactions"] = list(inter)
+    return st
+
+
+def ensemble_set(groups_per_cu=2, max_team=64, device=None):
+    ctx = context(device)
+    ctx.check(ctx.lib.nbody_ensemble_set(ctx.h, int(groups_per_cu), int(max_team)))
+
+
+def ensemble_info(device=None):
+    """(grid, teams) of the last ensemble launch."""
+    ctx = context(device)
+    g, t = ctypes.c_int32(), ctypes.c_int32()
+    ctx.check(ctx.lib.nbody_ensemble_info(ctx.h, ctypes.byref(g), ctypes.byref(t)))
+    return g.value, t.value
 
 
 class ForceShape(tuple):

@@ -22,6 +22,7 @@ NBODY_E_NOMEM = -5
 NBODY_ACC_FP32 = 0
 NBODY_ACC_DS = 1
 NBODY_FIXED_DT = 2
+NBODY_ADJ_ACCUMULATE = 4
 
 P = ctypes.c_void_p
 I64 = ctypes.c_int64
@@ -45,6 +46,13 @@ class NBodyForceConfig(ctypes.Structure):
                 ("min_j_wave", I32), ("target_groups", I32)]
 
 
+class NBodyEnsemble(ctypes.Structure):
+    """Mirror of ``nbody_ensemble`` in include/nbody.h."""
+    _fields_ = [("n_clusters", I32), ("offsets", P), ("eps2", P), ("t", P), ("dt", P),
+                ("x", P), ("v", P), ("a", P), ("k", P), ("m", P), ("eta", D), ("eta_s", D),
+                ("dt_max", D), ("dt_min", D), ("flags", U32)]
+
+
 # name -> (restype, argtypes); every symbol include/nbody.h declares
 SIGNATURES = {
     "nbody_version": (INT, []),
@@ -63,6 +71,9 @@ SIGNATURES = {
     "nbody_init": (INT, [P, ctypes.POINTER(NBodySystem), D]),
     "nbody_blockstep": (INT, [P, ctypes.POINTER(NBodySystem), I64, D,
                               ctypes.POINTER(I64), ctypes.POINTER(I64)]),
+    "nbody_ensemble_run": (INT, [P, ctypes.POINTER(NBodyEnsemble), D, P, P]),
+    "nbody_ensemble_set": (INT, [P, I32, I32]),
+    "nbody_ensemble_info": (INT, [P, ctypes.POINTER(I32), ctypes.POINTER(I32)]),
     "nbody_force_adjoint": (INT, [P, I64, P, P, P, D, P, P, P, P, P, P, U32]),
     "nbody_predict_adjoint": (INT, [P, I64, D, P, P, P, P, P, P]),
     "nbody_correct_adjoint": (INT, [P, I64, D, P, P, P, P, P, P, P, P]),

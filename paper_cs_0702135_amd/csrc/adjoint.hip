@@ -181,13 +181,11 @@ __global__ __launch_bounds__(64 * W) void force_adjoint_kernel(const KArgs a,
         }
         if (wave == 0 && slot < n) {
             if (S == 1) {
-                a.acc[slot] = tot[0];
-                a.acc[n + slot] = tot[1];
-                a.acc[2 * n + slot] = tot[2];
-                a.jerk[slot] = tot[3];
-                a.jerk[n + slot] = tot[4];
-                a.jerk[2 * n + slot] = tot[5];
-                a.pot[slot] = tot[6];
+                double *dst[7] = {&a.acc[slot],  &a.acc[n + slot],  &a.acc[2 * n + slot],
+                                  &a.jerk[slot], &a.jerk[n + slot], &a.jerk[2 * n + slot],
+                                  &a.pot[slot]};
+#pragma unroll
+                for (int c = 0; c < 7; ++c) *dst[c] = a.accumulate ? *dst[c] + tot[c] : tot[c];
             } else {
                 double *dst = a.part + (sp * 7) * n + slot;
 #pragma unroll
@@ -258,7 +256,8 @@ int nbody_force_adjoint(nbody_ctx *ctx, int64_t n, const double *pos, const doub
     if (!ctx) return NBODY_E_INVAL;
     if (n < 1 || n > 0x7fffffffLL || !(eps2 >= 0.0) || std::isinf(eps2))
         return fail(ctx, NBODY_E_INVAL, "nbody_force_adjoint: bad arguments");
-    if (flags & ~NBODY_ACC_DS) return fail(ctx, NBODY_E_INVAL, "nbody_force_adjoint: unknown flags");
+    if (flags & ~(NBODY_ACC_DS | NBODY_ADJ_ACCUMULATE))
+        return fail(ctx, NBODY_E_INVAL, "nbody_force_adjoint: unknown flags");
     if (!pos || !vel || !mass || !acc_bar || !jerk_bar || !pos_bar || !vel_bar || !mass_bar)
         return fail(ctx, NBODY_E_INVAL, "nbody_force_adjoint: null array");
     NB_TRY(activate(ctx));
@@ -282,6 +281,7 @@ int nbody_force_adjoint(nbody_ctx *ctx, int64_t n, const double *pos, const doub
     a.min_j_wave = 64;
     a.target_groups = 8 * ctx->cus;
     a.max_splits = kMaxSplits;
+    a.accumulate = (flags & NBODY_ADJ_ACCUMULATE) ? 1 : 0;
     const int64_t S = choose_splits(n, n, 1, W, a.min_j_wave, a.target_groups, a.max_splits);
     const int64_t nb = (n + 63) / 64;
     if (S > 1) {

@@ -149,7 +149,7 @@ int nbody_destroy(nbody_ctx *ctx) {
     if (!ctx) return NBODY_OK;
     (void)hipSetDevice(ctx->device);
     (void)hipStreamSynchronize(ctx->stream);
-    void *bufs[] = {ctx->jrec, ctx->part, ctx->work, ctx->bs, ctx->adj, ctx->info};
+    void *bufs[] = {ctx->jrec, ctx->part, ctx->work, ctx->bs, ctx->adj, ctx->ens, ctx->info};
     for (void *b : bufs)
         if (b) (void)hipFree(b);
     if (ctx->info_host) (void)hipHostFree(ctx->info_host);
@@ -238,6 +238,22 @@ int nbody_profile(nbody_ctx *ctx, int enable, double *force_ms, double *reduce_m
     if (force_ms) *force_ms = ctx->prof.force_ms;
     if (reduce_ms) *reduce_ms = ctx->prof.reduce_ms;
     if (launches) *launches = ctx->prof.launches;
+    return NBODY_OK;
+}
+
+int nbody_ensemble_set(nbody_ctx *ctx, int32_t groups_per_cu, int32_t max_team) {
+    if (!ctx) return NBODY_E_INVAL;
+    if (groups_per_cu < 1 || groups_per_cu > 8 || max_team < 1 || max_team > 4096)
+        return fail(ctx, NBODY_E_INVAL, "nbody_ensemble_set: bad values");
+    ctx->ens_groups_per_cu = groups_per_cu;
+    ctx->ens_max_team = max_team;
+    return NBODY_OK;
+}
+
+int nbody_ensemble_info(nbody_ctx *ctx, int32_t *grid, int32_t *teams) {
+    if (!ctx) return NBODY_E_INVAL;
+    if (grid) *grid = ctx->ens_last_grid;
+    if (teams) *teams = ctx->ens_last_teams;
     return NBODY_OK;
 }
 

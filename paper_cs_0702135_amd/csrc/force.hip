@@ -370,12 +370,9 @@ __global__ __launch_bounds__(64 * RW) void reduce_parts_kernel(const KArgs a, in
             double t = red[0][lane];
             for (int w = 1; w < RW; ++w) t += red[w][lane];
             const int64_t q = e / n_i, s = e - q * n_i;
-            if (q < 3)
-                a.acc[q * ostride + s] = t;
-            else if (q < 6)
-                a.jerk[(q - 3) * ostride + s] = t;
-            else if (a.pot)
-                a.pot[s] = t;
+            double *dst = q < 3 ? &a.acc[q * ostride + s]
+                                : (q < 6 ? &a.jerk[(q - 3) * ostride + s] : a.pot ? &a.pot[s] : nullptr);
+            if (dst) *dst = a.accumulate ? *dst + t : t;
         }
         __syncthreads();
     }
@@ -485,6 +482,7 @@ int launch_force(nbody_ctx *ctx, const ForceCall &c) {
     a.min_j_wave = sh.min_j_wave;
     a.target_groups = sh.target_groups;
     a.max_splits = kMaxSplits;
+    a.accumulate = 0;
 
     // Partial-sum scratch: S * 7 * n_i doubles.  When S > 1 the number of
     // i-blocks is below target_groups, so S * n_i <= 2 * target_groups * 64 * it.

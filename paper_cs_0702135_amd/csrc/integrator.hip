@@ -5,6 +5,7 @@
 #include <cmath>
 
 #include "common.hpp"
+#include "integ.hpp"
 
 namespace nb {
 
@@ -31,19 +32,14 @@ __global__ void predict_kernel(int64_t n, double t_target, const StepInfo *__res
     const double tt = info ? info->t_next : t_target;
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
          i += (int64_t)gridDim.x * blockDim.x) {
-        const double h = tt - t[i];
         double px[3], pv[3];
+        predict_one(tt - t[i], x, v, a, k, i, n, px, pv);
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
-            const int64_t q = c * n + i;
-            px[c] = x[q] + (v[q] + (h / 2.0) * (a[q] + (h / 3.0) * k[q])) * h;
-            pv[c] = v[q] + (a[q] + (h / 2.0) * k[q]) * h;
-            xp[q] = px[c];
-            vp[q] = pv[c];
+            xp[c * n + i] = px[c];
+            vp[c * n + i] = pv[c];
         }
-        if (jrec) {
-            store_rec(rep, jrec + i, px[0], px[1], px[2], pv[0], pv[1], pv[2], mass[i]);
-        }
+        if (jrec) store_rec(rep, jrec + i, px[0], px[1], px[2], pv[0], pv[1], pv[2], mass[i]);
     }
 }
 
@@ -260,50 +256,15 @@ __global__ void correct_kernel(int64_t n, int64_t n_i_arg, const StepInfo *__res
             latch(sinfo, ST_INDEX);
             continue;
         }
-        const double h = dtv[i];
-        const double t_new = t[i] + h;
-        double a1v[3], k1v[3], a2v[3], a3v[3];
+        double a1v[3], k1v[3];
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
-            const int64_t q = c * n + i;
-            const double a0 = a[q], k0 = k[q];
-            const double a1 = acc_new[c * sn + s], k1 = jerk_new[c * sn + s];
-            const double A3 = 2.0 * (a0 - a1) + (k0 + k1) * h;
-            const double A2 = -3.0 * (a0 - a1) - (2.0 * k0 + k1) * h;
-            x[q] = xp[q] + (A2 / 12.0 + A3 / 20.0) * h * h;
-            v[q] = vp[q] + (A2 / 3.0 + A3 / 4.0) * h;
-            a[q] = a1;
-            k[q] = k1;
-            a1v[c] = a1;
-            k1v[c] = k1;
-            a2v[c] = (2.0 * A2 + 6.0 * A3) / (h * h);
-            a3v[c] = 6.0 * A3 / (h * h * h);
+            a1v[c] = acc_new[c * sn + s];
+            k1v[c] = jerk_new[c * sn + s];
         }
-        t[i] = t_new;
-        if (!fixed_dt) {
-            const double an = sqrt(a1v[0] * a1v[0] + a1v[1] * a1v[1] + a1v[2] * a1v[2]);
-            const double kn = sqrt(k1v[0] * k1v[0] + k1v[1] * k1v[1] + k1v[2] * k1v[2]);
-            const double a2n = sqrt(a2v[0] * a2v[0] + a2v[1] * a2v[1] + a2v[2] * a2v[2]);
-            const double a3n = sqrt(a3v[0] * a3v[0] + a3v[1] * a3v[1] + a3v[2] * a3v[2]);
-            const double num = eta * (an * a2n + kn * kn);
-            const double den = kn * a3n + a2n * a2n;
-            double crit = den > 0.0 ? sqrt(num / den) : INFINITY;
-            double d = h;
-            if (!(crit == crit)) {
-                latch(sinfo, ST_NONFINITE);
-                crit = d;
-            }
-            if (d > crit) {
-                while (d > crit) d = d / 2.0;
-            } else if (2.0 * d <= crit && fmod(t_new, 2.0 * d) == 0.0 && 2.0 * d <= dt_max) {
-                d = 2.0 * d;
-            }
-            if (d < dt_min) {
-                latch(sinfo, ST_RANGE);
-                d = dt_min;
-            }
-            dtv[i] = d;
-        }
+        const int32_t st = correct_one(i, n, xp, vp, a1v, k1v, eta, dt_max, dt_min, fixed_dt, t,
+                                       dtv, x, v, a, k);
+        if (st) latch(sinfo, st);
     }
 }
 
@@ -314,20 +275,9 @@ __global__ void initial_dt_kernel(int64_t n, double t0, const double *__restrict
 #pragma clang fp contract(off)
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
          i += (int64_t)gridDim.x * blockDim.x) {
-        const double ax = a[i], ay = a[n + i], az = a[2 * n + i];
-        const double kx = k[i], ky = k[n + i], kz = k[2 * n + i];
-        const double an = sqrt(ax * ax + ay * ay + az * az);
-        const double kn = sqrt(kx * kx + ky * ky + kz * kz);
-        double want = kn > 0.0 ? eta_s * an / kn : dt_max;
-        if (!(want == want)) {
-            latch(info, ST_NONFINITE);
-            want = dt_min;
-        }
-        double d = dt_max;
-        while (d > want && d >= 2.0 * dt_min) d = d / 2.0;
-        while (fmod(t0, d) != 0.0 && d >= 2.0 * dt_min) d = d / 2.0;
-        if (d > want || fmod(t0, d) != 0.0) latch(info, ST_RANGE);
-        dt[i] = d;
+        int32_t st = 0;
+        dt[i] = initial_dt_one(i, n, t0, a, k, eta_s, dt_max, dt_min, &st);
+        if (st) latch(info, st);
     }
 }
 

@@ -31,6 +31,7 @@ struct KArgs {
     int32_t min_j_wave;
     int32_t target_groups;
     int32_t max_splits;
+    int32_t accumulate;  // 1: add into acc/jerk/pot instead of overwriting
 };
 
 // Number of workgroups that share one i-block's j range.
