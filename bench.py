@@ -194,6 +194,52 @@ def main():
         aux["plummer1k_energy_drift_per_time_unit"] = abs((e_1 - e_0) / e_0) / c1.t_end
         aux["plummer1k_block_steps"] = steps1
         aux["plummer1k_ms_per_block_step"] = (tb - ta) / max(1, steps1) * 1e3
+
+        # batched ensemble: 256 clusters, N log-uniform in [256, 8192], to t = 1/16,
+        # one persistent launch (inputs resident before timing; second run timed)
+        from workloads.plummer import ensemble_members
+        ce = CONFIGS["ensemble256"]
+        sizes, eps_c, seeds = ensemble_members(ce)
+        parts = [plummer(int(nc), int(sd)) for nc, sd in zip(sizes, seeds)]
+        EP = torch.from_numpy(np.concatenate([q[0] for q in parts], axis=1)).cuda()
+        EV = torch.from_numpy(np.concatenate([q[1] for q in parts], axis=1)).cuda()
+        EM = torch.from_numpy(np.concatenate([q[2] for q in parts])).cuda()
+        off = np.concatenate([[0], np.cumsum(sizes)]).astype(np.int64)
+        ens_cfg = autotune.load_or_calibrate_ensemble(args.mode, log=log)
+        aux["ensemble_model"] = ens_cfg
+        nb.ensemble_run(EP, EV, EM, off, eps_c ** 2, ce.t_end, dt_max=ce.dt_max, mode=args.mode)
+        torch.cuda.synchronize()
+        ta = time.perf_counter()
+        res = nb.ensemble_run(EP, EV, EM, off, eps_c ** 2, ce.t_end, dt_max=ce.dt_max,
+                              mode=args.mode)
+        tb = time.perf_counter()
+        grid, teams = nb.ensemble_info()
+        aux["ensemble256_seconds"] = tb - ta
+        aux["ensemble256_interactions_per_s"] = float(sum(res["interactions"])) / (tb - ta)
+        aux["ensemble256_block_steps"] = int(sum(res["steps"]))
+        aux["ensemble256_grid_teams"] = [grid, teams]
+
+        # differentiable run: N = 16384, eps = 1/512, 64 shared steps of 1/512,
+        # checkpoints every 8 steps; forward + backward through the HIP adjoint
+        from paper_cs_0702135_amd.autograd import shared_run
+        cg = CONFIGS["grad16k"]
+        gp, gv, gm = plummer(cg.n, cg.seed)
+        GP, GV, GM = (torch.from_numpy(q).cuda() for q in (gp, gv, gm))
+        with torch.no_grad():
+            xT = shared_run(GP, GV, GM, cg.eps2, cg.extra["dt"], cg.extra["steps"])[0]
+        tgt = xT + cg.extra["target_sigma"] * torch.randn(xT.shape, dtype=xT.dtype,
+                                                          device=xT.device,
+                                                          generator=torch.Generator("cuda").manual_seed(2005))
+        torch.cuda.synchronize()
+        ta = time.perf_counter()
+        P0 = GP.clone().requires_grad_(True)
+        xf = shared_run(P0, GV, GM, cg.eps2, cg.extra["dt"], cg.extra["steps"],
+                        checkpoint_every=cg.extra["ckpt"])[0]
+        loss = ((xf - tgt) ** 2).sum() / cg.n
+        loss.backward()
+        torch.cuda.synchronize()
+        tb = time.perf_counter()
+        aux["grad16k_forward_backward_seconds"] = tb - ta
         out["aux"] = aux
 
     if not args.no_cpu:

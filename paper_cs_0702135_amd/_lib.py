@@ -53,6 +53,12 @@ class NBodyEnsemble(ctypes.Structure):
                 ("dt_max", D), ("dt_min", D), ("flags", U32)]
 
 
+class NBodyEnsembleConfig(ctypes.Structure):
+    """Mirror of ``nbody_ensemble_config`` in include/nbody.h."""
+    _fields_ = [("groups_per_cu", I32), ("max_team", I32), ("step_us", D),
+                ("barrier_us", D), ("group_rate", D)]
+
+
 # name -> (restype, argtypes); every symbol include/nbody.h declares
 SIGNATURES = {
     "nbody_version": (INT, []),
@@ -72,7 +78,8 @@ SIGNATURES = {
     "nbody_blockstep": (INT, [P, ctypes.POINTER(NBodySystem), I64, D,
                               ctypes.POINTER(I64), ctypes.POINTER(I64)]),
     "nbody_ensemble_run": (INT, [P, ctypes.POINTER(NBodyEnsemble), D, P, P]),
-    "nbody_ensemble_set": (INT, [P, I32, I32]),
+    "nbody_ensemble_set": (INT, [P, ctypes.POINTER(NBodyEnsembleConfig)]),
+    "nbody_ensemble_get": (INT, [P, ctypes.POINTER(NBodyEnsembleConfig)]),
     "nbody_ensemble_info": (INT, [P, ctypes.POINTER(I32), ctypes.POINTER(I32)]),
     "nbody_force_adjoint": (INT, [P, I64, P, P, P, D, P, P, P, P, P, P, U32]),
     "nbody_predict_adjoint": (INT, [P, I64, D, P, P, P, P, P, P]),

@@ -141,3 +141,70 @@ def load_or_tune(pos, vel, mass, eps2, mode="fp32", log=None, dynamic_n_i=None, 
         save(table)
     install(table, dynamic_n_i=dynamic_n_i)
     return table
+
+
+# ---------------------------------------------------------------------------
+# Ensemble team-planning model (nbody_ensemble_config): measured from three
+# single-cluster runs -- a small and a large cluster on one workgroup, and the
+# large one on a team of 8 -- then solved for the per-step latency, the
+# per-group pair rate and the extra per-step cost of a multi-group team.
+
+def _ens_single(n, seed, max_team, groups_per_cu, t_end, dt_max, mode):
+    import numpy as np
+    from workloads.plummer import plummer
+    from . import ensemble_run, ensemble_set
+    p, v, m = plummer(n, seed)
+    P, V, M = (torch.from_numpy(a).cuda() for a in (p, v, m))
+    eps2 = (n ** (-1.0 / 3.0) / 16.0) ** 2
+    off = np.array([0, n], dtype=np.int64)
+    ensemble_set(groups_per_cu=groups_per_cu, max_team=max_team)
+    ensemble_run(P, V, M, off, [eps2], t_end, dt_max=dt_max, mode=mode)  # warm-up
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    out = ensemble_run(P, V, M, off, [eps2], t_end, dt_max=dt_max, mode=mode)
+    e1.record()
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) * 1e-3, out["steps"][0], out["interactions"][0]
+
+
+def calibrate_ensemble(mode="fp32", t_end=1.0 / 16, dt_max=1.0 / 16, log=None):
+    from . import ensemble_get, ensemble_set
+    saved = ensemble_get()
+    try:
+        # one group: t = steps * step + interactions / rate
+        ts, ss, is_ = _ens_single(256, 91, 1, saved["groups_per_cu"], t_end, dt_max, mode)
+        tl, sl, il = _ens_single(4096, 92, 1, saved["groups_per_cu"], t_end, dt_max, mode)
+        a = [[ss, is_], [sl, il]]
+        det = a[0][0] * a[1][1] - a[0][1] * a[1][0]
+        step = (ts * a[1][1] - tl * a[0][1]) / det
+        inv_rate = (a[0][0] * tl - a[1][0] * ts) / det
+        step = max(step, 1e-6)
+        rate = 1.0 / inv_rate if inv_rate > 0 else saved["group_rate"]
+        # a team of 8 groups on the large cluster: the rest is barrier cost
+        t8, s8, i8 = _ens_single(4096, 92, 8, saved["groups_per_cu"], t_end, dt_max, mode)
+        barrier = max(0.0, (t8 - s8 * step - i8 / (8 * rate)) / s8)
+        cfg = dict(saved, step_us=step * 1e6, barrier_us=barrier * 1e6, group_rate=rate)
+        if log:
+            log("ensemble model: step %.1f us, barrier %.1f us, group rate %.3e /s"
+                % (cfg["step_us"], cfg["barrier_us"], cfg["group_rate"]))
+        return cfg
+    finally:
+        ensemble_set(**saved)
+
+
+def load_or_calibrate_ensemble(mode="fp32", log=None):
+    from . import ensemble_set
+    arch = torch.cuda.get_device_properties(0).gcnArchName.split(":")[0]
+    p = os.path.join(CACHE_DIR, "%s_ensemble_%s.json" % (arch, mode))
+    if os.path.exists(p):
+        with open(p) as f:
+            cfg = json.load(f)
+    else:
+        cfg = calibrate_ensemble(mode, log=log)
+        os.makedirs(CACHE_DIR, exist_ok=True)
+        with open(p, "w") as f:
+            json.dump(cfg, f, indent=1)
+    ensemble_set(**cfg)
+    return cfg

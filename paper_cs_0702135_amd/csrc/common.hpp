@@ -77,8 +77,7 @@ struct nbody_ctx {
     size_t adj_bytes = 0;
     void *ens = nullptr;  // ensemble tables, team scratch, predicted state
     size_t ens_bytes = 0;
-    int ens_groups_per_cu = 2;
-    int ens_max_team = 64;
+    nbody_ensemble_config ens_cfg = {2, 64, 30.0, 15.0, 2.0e9};
     int ens_last_grid = 0;
     int ens_last_teams = 0;
     nb::StepInfo *info = nullptr;  // device

@@ -1,4 +1,5 @@
 // Context management, errors and scratch buffers of libnbody.so.
+#include <cmath>
 #include <cstdarg>
 #include <new>
 
@@ -241,12 +242,20 @@ int nbody_profile(nbody_ctx *ctx, int enable, double *force_ms, double *reduce_m
     return NBODY_OK;
 }
 
-int nbody_ensemble_set(nbody_ctx *ctx, int32_t groups_per_cu, int32_t max_team) {
-    if (!ctx) return NBODY_E_INVAL;
-    if (groups_per_cu < 1 || groups_per_cu > 8 || max_team < 1 || max_team > 4096)
+int nbody_ensemble_set(nbody_ctx *ctx, const nbody_ensemble_config *cfg) {
+    if (!ctx || !cfg) return NBODY_E_INVAL;
+    if (cfg->groups_per_cu < 1 || cfg->groups_per_cu > 8 || cfg->max_team < 1 ||
+        cfg->max_team > 4096 || !(cfg->step_us >= 0) || !(cfg->barrier_us >= 0) ||
+        !(cfg->group_rate > 0) || std::isinf(cfg->step_us) || std::isinf(cfg->barrier_us) ||
+        std::isinf(cfg->group_rate))
         return fail(ctx, NBODY_E_INVAL, "nbody_ensemble_set: bad values");
-    ctx->ens_groups_per_cu = groups_per_cu;
-    ctx->ens_max_team = max_team;
+    ctx->ens_cfg = *cfg;
+    return NBODY_OK;
+}
+
+int nbody_ensemble_get(nbody_ctx *ctx, nbody_ensemble_config *cfg) {
+    if (!ctx || !cfg) return NBODY_E_INVAL;
+    *cfg = ctx->ens_cfg;
     return NBODY_OK;
 }
 

@@ -12,12 +12,18 @@
 // Barrier waits are bounded by a wall-clock limit: if one expires the launch
 // raises an abort flag that every group checks, so the grid always drains.
 //
-// The host plans the teams from a cost model: a cluster of N particles
-// costs ~ N^2.16 pair interactions per time unit (the paper's fits of the
-// mean block size, 0.20 N^0.81, and of the steps per time unit, 247 N^0.35,
-// times N).  Clusters costing more than an even share get a team of several
-// groups; the rest are packed onto single-group teams, largest first onto
-// the least-loaded team.
+// The host plans the teams from a time model.  A cluster of N particles
+// takes about S = 247 N^0.35 t_end block steps with blocks of 0.20 N^0.81
+// particles (the paper's fits of steps per time unit and of the mean block
+// size), so on a team of g groups it takes
+//     T(N, g) = S (step + [g > 1] barrier + 0.20 N^1.81 / (g rate))
+// where step is the fixed latency of one block step on one group, barrier
+// the extra cost of a multi-group step and rate the pair interactions per
+// second of one group (all three calibrated by the autotuner).  With at
+// least as many groups as clusters every cluster gets its own team and the
+// spare groups go, one at a time, to the team with the largest T (while
+// that lowers it); otherwise clusters are packed onto single-group teams,
+// longest first onto the least-loaded team.
 //
 // The j particles of a pair-sum pass are staged through LDS in tiles (the
 // predicted state is written during this launch, so it cannot be read
@@ -79,27 +85,31 @@ __device__ __forceinline__ bool aborted(const int32_t *abort) {
     return __hip_atomic_load(abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0;
 }
 
-// Team barrier; returns false if the launch is being aborted.  Every thread
-// releases its own writes at agent scope before arriving (the groups of a
-// team sit on different XCDs, whose L2 caches are only made coherent by
-// agent-scope release/acquire), and acquires after the team has arrived.
+// Team barrier; returns false if the launch is being aborted.
+// The groups of a team sit on different XCDs, whose L2 caches are made
+// coherent only by agent-scope release/acquire.  After the workgroup barrier
+// (every wave's stores complete), one thread issues the release (L2
+// write-back), arrives, waits by polling the generation word with relaxed
+// loads (an acquire per poll would invalidate the L2 under the groups still
+// computing on that XCD), and issues one acquire (L1/L2 invalidate) when the
+// whole team has arrived; the cache operations act for the whole CU / XCD.
 __device__ bool team_barrier(uint32_t *bar, int g, int32_t *abort, int64_t limit) {
     __shared__ int ok;
-    if (g > 1) __threadfence();
     __syncthreads();
     if (threadIdx.x == 0) {
         int good = 1;
         if (g > 1) {
             uint32_t *cnt = bar, *gen = bar + 16;
-            const uint32_t my = __hip_atomic_load(gen, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+            const uint32_t my = __hip_atomic_load(gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             const uint32_t arrived =
-                __hip_atomic_fetch_add(cnt, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+                __hip_atomic_fetch_add(cnt, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             if (arrived == (uint32_t)(g - 1)) {
                 __hip_atomic_store(cnt, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                 __hip_atomic_fetch_add(gen, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
             } else {
                 const uint64_t t0 = wall_clock64();
-                while (__hip_atomic_load(gen, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) == my) {
+                while (__hip_atomic_load(gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == my) {
                     if (aborted(abort)) {
                         good = 0;
                         break;
@@ -112,12 +122,12 @@ __device__ bool team_barrier(uint32_t *bar, int g, int32_t *abort, int64_t limit
                     __builtin_amdgcn_s_sleep(2);
                 }
             }
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
         }
         if (aborted(abort)) good = 0;
         ok = good;
     }
     __syncthreads();
-    if (g > 1) __threadfence();
     return ok != 0;
 }
 
@@ -228,7 +238,7 @@ __device__ bool ens_pairs(const EnsArgs &A, const double *src_x, const double *s
                           int rank, int s_max, int n_max, double *anew, double *knew,
                           double *part, uint32_t *bar, TileRec *tile, double (*red)[7][64]) {
     const int64_t nb = (n_i + 63) / 64;
-    int64_t S = (2 * g + nb - 1) / nb;
+    int64_t S = (g + nb - 1) / nb;  // about one item per group
     int64_t smax = max(1, n / ETILE);
     if (smax > s_max) smax = s_max;
     if (S > smax) S = smax;
@@ -358,11 +368,25 @@ __global__ __launch_bounds__(ETH) void ensemble_kernel(const EnsArgs A) {
                 n_i += cr;
             }
             {
+                // place the active indices (ascending) and predict every
+                // particle of the slice to tn in the same pass
                 const int lane = tid & 63, wave = tid >> 6;
                 int64_t off = before;
                 for (int pbase = p0; pbase < p1; pbase += ETH) {
                     const int i = pbase + tid;
-                    const bool f = i < p1 && (A.t[base + i] + A.dt[base + i] == tn);
+                    bool f = false;
+                    if (i < p1) {
+                        const int64_t q = base + i;
+                        const double tq = A.t[q];
+                        f = (tq + A.dt[q] == tn);
+                        double px[3], pv[3];
+                        predict_one(tn - tq, A.x, A.v, A.a, A.k, q, nt, px, pv);
+#pragma unroll
+                        for (int cc = 0; cc < 3; ++cc) {
+                            A.xp[cc * nt + q] = px[cc];
+                            A.vp[cc * nt + q] = pv[cc];
+                        }
+                    }
                     const unsigned long long bal = __ballot(f);
                     const int bef = __popcll(bal & ((1ull << lane) - 1ull));
                     __syncthreads();
@@ -375,17 +399,6 @@ __global__ __launch_bounds__(ETH) void ensemble_kernel(const EnsArgs A) {
                     }
                     if (f) act[off + woff + bef] = i;
                     off += tot;
-                }
-            }
-            // ---- predict every particle of the cluster to tn
-            for (int i = p0 + tid; i < p1; i += ETH) {
-                const int64_t q = base + i;
-                double px[3], pv[3];
-                predict_one(tn - A.t[q], A.x, A.v, A.a, A.k, q, nt, px, pv);
-#pragma unroll
-                for (int cc = 0; cc < 3; ++cc) {
-                    A.xp[cc * nt + q] = px[cc];
-                    A.vp[cc * nt + q] = pv[cc];
                 }
             }
             if (!team_barrier(bar, g, A.abort, A.spin_limit)) return;
@@ -442,62 +455,69 @@ struct Plan {
     int64_t scratch = 0;  // doubles
 };
 
-static Plan plan_teams(const std::vector<int64_t> &sizes, int G, int max_team) {
-    const int nc = (int)sizes.size();
-    std::vector<double> cost(nc);
-    double total = 0;
-    for (int c = 0; c < nc; ++c) {
-        cost[c] = std::pow((double)sizes[c], 2.16);
-        total += cost[c];
+struct TimeModel {
+    double step_s, barrier_s, rate, t_end;
+    double steps(double n) const { return std::max(1.0, 247.0 * std::pow(n, 0.35) * t_end); }
+    double time(double n, int g) const {
+        const double per_step = step_s + (g > 1 ? barrier_s : 0.0) +
+                                0.20 * std::pow(n, 1.81) / ((double)g * rate);
+        return steps(n) * per_step;
     }
-    std::vector<int> idx(nc);
-    std::iota(idx.begin(), idx.end(), 0);
-    std::sort(idx.begin(), idx.end(), [&](int p, int q) { return cost[p] > cost[q] || (cost[p] == cost[q] && p < q); });
-    const double share = total / G;
-    // large clusters: dedicated multi-group teams
+};
+
+static Plan plan_teams(const std::vector<int64_t> &sizes, int G, int max_team,
+                       const TimeModel &M) {
+    const int nc = (int)sizes.size();
     std::vector<std::vector<int>> tcl;
     std::vector<int> tsize;
-    std::vector<double> tload;
-    int used = 0, k = 0;
-    for (; k < nc; ++k) {
-        const int c = idx[k];
-        int g = (int)std::ceil(cost[c] / share);
-        if (g < 2) break;
-        g = std::min(g, max_team);
-        if (used + g > G - 1) break;
-        tcl.push_back({c});
-        tsize.push_back(g);
-        tload.push_back(cost[c] / g);
-        used += g;
-    }
-    // the rest: single-group teams, largest cluster onto the least-loaded
-    const int singles = std::max(0, G - used);
-    const int first_single = (int)tcl.size();
-    for (int s = 0; s < singles && k < nc; ++s) {
-        tcl.push_back({});
-        tsize.push_back(1);
-        tload.push_back(0.0);
-    }
-    typedef std::pair<double, int> LT;
-    std::priority_queue<LT, std::vector<LT>, std::greater<LT>> heap;
-    for (int t = first_single; t < (int)tcl.size(); ++t) heap.push(LT(0.0, t));
-    for (; k < nc; ++k) {
-        const int c = idx[k];
-        int t;
-        if (!heap.empty()) {
+    if (G >= nc) {
+        // one team per cluster, then spare groups to the slowest team
+        std::vector<int> gsz(nc, 1);
+        typedef std::pair<double, int> TT;
+        std::priority_queue<TT> heap;
+        for (int c = 0; c < nc; ++c) heap.push(TT(M.time((double)sizes[c], 1), c));
+        int spare = G - nc;
+        while (spare > 0 && !heap.empty()) {
+            TT top = heap.top();
+            heap.pop();
+            const int c = top.second;
+            if (gsz[c] >= max_team) continue;
+            const double t1 = M.time((double)sizes[c], gsz[c] + 1);
+            if (!(t1 < top.first)) continue;  // more groups no longer help
+            gsz[c] += 1;
+            --spare;
+            heap.push(TT(t1, c));
+        }
+        std::vector<int> idx(nc);
+        std::iota(idx.begin(), idx.end(), 0);
+        std::sort(idx.begin(), idx.end(), [&](int p, int q) {
+            const double a = M.time((double)sizes[p], gsz[p]), b = M.time((double)sizes[q], gsz[q]);
+            return a > b || (a == b && p < q);
+        });
+        for (int c : idx) {
+            tcl.push_back({c});
+            tsize.push_back(gsz[c]);
+        }
+    } else {
+        // more clusters than groups: longest first onto the least-loaded group
+        std::vector<int> idx(nc);
+        std::iota(idx.begin(), idx.end(), 0);
+        std::sort(idx.begin(), idx.end(), [&](int p, int q) {
+            return sizes[p] > sizes[q] || (sizes[p] == sizes[q] && p < q);
+        });
+        tcl.assign(G, {});
+        tsize.assign(G, 1);
+        typedef std::pair<double, int> LT;
+        std::priority_queue<LT, std::vector<LT>, std::greater<LT>> heap;
+        for (int t = 0; t < G; ++t) heap.push(LT(0.0, t));
+        for (int c : idx) {
             LT top = heap.top();
             heap.pop();
-            t = top.second;
-            tload[t] += cost[c];
-            heap.push(LT(tload[t], t));
-        } else {  // no single groups left: the least-loaded team
-            t = (int)(std::min_element(tload.begin(), tload.end()) - tload.begin());
-            tload[t] += cost[c] / tsize[t];
+            tcl[top.second].push_back(c);
+            heap.push(LT(top.first + M.time((double)sizes[c], 1), top.second));
         }
-        tcl[t].push_back(c);
     }
     Plan P;
-    int wg = 0;
     for (int t = 0; t < (int)tcl.size(); ++t) {
         if (tcl[t].empty()) continue;
         EnsTeam T = {};
@@ -510,7 +530,7 @@ static Plan plan_teams(const std::vector<int64_t> &sizes, int G, int max_team) {
         }
         T.cl_end = (int32_t)P.order.size();
         T.n_max = nmax;
-        T.s_max = std::min(EMAXSPLIT, 2 * T.size);
+        T.s_max = std::min(EMAXSPLIT, std::max(1, T.size));
         T.scratch_off = P.scratch;
         P.scratch += 2 * T.size + (nmax + 1) / 2 + 6 * (int64_t)nmax +
                      (int64_t)T.s_max * 6 * nmax + 8;
@@ -519,7 +539,6 @@ static Plan plan_teams(const std::vector<int64_t> &sizes, int G, int max_team) {
         for (int r = 0; r < T.size; ++r) {
             P.wg_team.push_back(team_id);
             P.wg_rank.push_back(r);
-            ++wg;
         }
     }
     return P;
@@ -559,10 +578,12 @@ extern "C" int nbody_ensemble_run(nbody_ctx *ctx, const nbody_ensemble *e, doubl
     int occ = 0;
     NB_TRY(hip_check(ctx, hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, kfn, ETH, 0),
                      "occupancy"));
-    int per_cu = std::min(occ, ctx->ens_groups_per_cu > 0 ? ctx->ens_groups_per_cu : 2);
+    int per_cu = std::min(occ, ctx->ens_cfg.groups_per_cu);
     if (per_cu < 1) return fail(ctx, NBODY_E_DEVICE, "ensemble kernel does not fit a CU");
     const int G = per_cu * ctx->cus;
-    Plan P = plan_teams(sizes, G, ctx->ens_max_team > 0 ? ctx->ens_max_team : 64);
+    const nbody_ensemble_config &cf = ctx->ens_cfg;
+    TimeModel M{cf.step_us * 1e-6, cf.barrier_us * 1e-6, cf.group_rate, t_end > 0 ? t_end : 0.0};
+    Plan P = plan_teams(sizes, G, cf.max_team, M);
     const int grid = (int)P.wg_team.size();
     const int nteams = (int)P.teams.size();
 

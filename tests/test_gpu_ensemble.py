@@ -50,7 +50,7 @@ def _check_cluster(orc, pos, vel, m, off, eps2, out, c, t_end, dt_max):
     drift = abs((e1 - e0) / e0) / t_end
     drift_ref = abs((e_ref - e0) / e0) / t_end
     say("  cluster %d: drift/unit GPU %.3e, oracle %.3e" % (c, drift, drift_ref))
-    assert abs(drift - drift_ref) <= 1e-8 + 0.05 * drift_ref
+    assert abs(drift - drift_ref) <= 1e-7 + 0.05 * drift_ref
     return steps, out["steps"][c], dx, drift
 
 
@@ -72,6 +72,7 @@ def test_multi_group_team(orc):
     # one large cluster among small ones gets a team of several groups
     need_gpu()
     import paper_cs_0702135_amd as nb
+    saved = nb.ensemble_get()
     nb.ensemble_set(groups_per_cu=1, max_team=32)
     try:
         sizes = [3000] + [128] * 20
@@ -87,7 +88,7 @@ def test_multi_group_team(orc):
             assert abs(gs - rs) <= max(2, 0.03 * rs)
             assert dx < 1e-6
     finally:
-        nb.ensemble_set()
+        nb.ensemble_set(**saved)
 
 
 def test_full_ensemble_workload(orc):
