@@ -227,22 +227,32 @@ int nbody_ensemble_run(nbody_ctx *ctx, const nbody_ensemble *e, double t_end,
 
 /* Launch shape and team-planning model of the ensemble.  The persistent grid
  * has groups_per_cu workgroups per CU (capped by occupancy); a cluster of N
- * particles is modelled to take S = 247 N^0.35 t_end block steps of
- * 0.20 N^0.81 active particles (the paper's fits), i.e. on a team of g groups
- *   T = S (step_us + [g > 1] barrier_us) 1e-6 + S 0.20 N^1.81 / (g group_rate),
- * and teams (at most max_team groups) are sized to even out T. */
+ * particles is modelled to take S = steps_coef N^steps_exp t_end block steps
+ * of 0.20 N^0.81 active particles (the paper fits 247 N^0.35 steps per time
+ * unit and that block size), i.e. on a team of g groups
+ *   T = S (step_us + [g > 1] (barrier_us + barrier_group_us g)) 1e-6
+ *       + S 0.20 N^1.81 / (g group_rate),
+ * and teams (at most min(max_team, 64) groups) are sized to even out T. */
 typedef struct nbody_ensemble_config {
     int32_t groups_per_cu; /* 1..8 */
     int32_t max_team;      /* 1..4096 */
     double step_us;        /* fixed latency of one block step on one group */
-    double barrier_us;     /* extra per-step cost of a multi-group team */
+    double barrier_us;     /* extra per-step cost of a multi-group team ... */
+    double barrier_group_us; /* ... plus this much per group of the team */
     double group_rate;     /* pair interactions per second of one group */
+    double steps_coef;     /* block steps per time unit = steps_coef N^steps_exp */
+    double steps_exp;
 } nbody_ensemble_config;
 
 int nbody_ensemble_set(nbody_ctx *ctx, const nbody_ensemble_config *cfg);
 /* Current configuration (HOST output). */
 int nbody_ensemble_get(nbody_ctx *ctx, nbody_ensemble_config *cfg);
 
+/* Per cluster of the last ensemble launch (HOST outputs, n_clusters entries,
+ * either may be NULL): wall-clock seconds from the start of its
+ * initialisation to its last step, and the number of groups of its team. */
+int nbody_ensemble_timing(nbody_ctx *ctx, int32_t n_clusters, double *seconds,
+                          int32_t *groups);
 /* Grid size and number of teams of the last ensemble launch (HOST outputs). */
 int nbody_ensemble_info(nbody_ctx *ctx, int32_t *grid, int32_t *teams);
 

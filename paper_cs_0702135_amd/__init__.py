@@ -26,7 +26,7 @@ __all__ = [
     "correct", "initial_dt", "energy", "System", "ACC_FP32", "ACC_DS",
     "ForceShape", "tune_set", "tune_clear", "tune_get", "profile",
     "force_adjoint", "predict_adjoint", "correct_adjoint", "ensemble_run",
-    "ensemble_set", "ensemble_get", "ensemble_info",
+    "ensemble_set", "ensemble_get", "ensemble_info", "ensemble_timing",
 ]
 
 ACC_FP32 = L.NBODY_ACC_FP32
@@ -290,13 +290,16 @@ def ensemble_run(pos, vel, mass, offsets, eps2, t_end, eta=0.02, eta_s=0.01, dt_
 
 
 def ensemble_set(groups_per_cu=None, max_team=None, step_us=None, barrier_us=None,
-                 group_rate=None, device=None):
+                 barrier_group_us=None, group_rate=None, steps_coef=None, steps_exp=None,
+                 device=None):
     """Change the ensemble launch shape / team-planning model (None keeps)."""
     ctx = context(device)
     c = L.NBodyEnsembleConfig()
     ctx.check(ctx.lib.nbody_ensemble_get(ctx.h, ctypes.byref(c)))
     for k, v in (("groups_per_cu", groups_per_cu), ("max_team", max_team), ("step_us", step_us),
-                 ("barrier_us", barrier_us), ("group_rate", group_rate)):
+                 ("barrier_us", barrier_us), ("barrier_group_us", barrier_group_us),
+                 ("group_rate", group_rate),
+                 ("steps_coef", steps_coef), ("steps_exp", steps_exp)):
         if v is not None:
             setattr(c, k, v)
     ctx.check(ctx.lib.nbody_ensemble_set(ctx.h, ctypes.byref(c)))
@@ -307,6 +310,15 @@ def ensemble_get(device=None):
     c = L.NBodyEnsembleConfig()
     ctx.check(ctx.lib.nbody_ensemble_get(ctx.h, ctypes.byref(c)))
     return {k: getattr(c, k) for k, _ in L.NBodyEnsembleConfig._fields_}
+
+
+def ensemble_timing(n_clusters, device=None):
+    """(seconds, groups) per cluster of the last ensemble launch."""
+    ctx = context(device)
+    sec = (ctypes.c_double * n_clusters)()
+    grp = (ctypes.c_int32 * n_clusters)()
+    ctx.check(ctx.lib.nbody_ensemble_timing(ctx.h, int(n_clusters), sec, grp))
+    return list(sec), list(grp)
 
 
 def ensemble_info(device=None):

@@ -56,7 +56,8 @@ class NBodyEnsemble(ctypes.Structure):
 class NBodyEnsembleConfig(ctypes.Structure):
     """Mirror of ``nbody_ensemble_config`` in include/nbody.h."""
     _fields_ = [("groups_per_cu", I32), ("max_team", I32), ("step_us", D),
-                ("barrier_us", D), ("group_rate", D)]
+                ("barrier_us", D), ("barrier_group_us", D), ("group_rate", D),
+                ("steps_coef", D), ("steps_exp", D)]
 
 
 # name -> (restype, argtypes); every symbol include/nbody.h declares
@@ -80,6 +81,7 @@ SIGNATURES = {
     "nbody_ensemble_run": (INT, [P, ctypes.POINTER(NBodyEnsemble), D, P, P]),
     "nbody_ensemble_set": (INT, [P, ctypes.POINTER(NBodyEnsembleConfig)]),
     "nbody_ensemble_get": (INT, [P, ctypes.POINTER(NBodyEnsembleConfig)]),
+    "nbody_ensemble_timing": (INT, [P, I32, P, P]),
     "nbody_ensemble_info": (INT, [P, ctypes.POINTER(I32), ctypes.POINTER(I32)]),
     "nbody_force_adjoint": (INT, [P, I64, P, P, P, D, P, P, P, P, P, P, U32]),
     "nbody_predict_adjoint": (INT, [P, I64, D, P, P, P, P, P, P]),

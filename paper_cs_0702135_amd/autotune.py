@@ -144,51 +144,98 @@ def load_or_tune(pos, vel, mass, eps2, mode="fp32", log=None, dynamic_n_i=None, 
 
 
 # ---------------------------------------------------------------------------
-# Ensemble team-planning model (nbody_ensemble_config): measured from three
-# single-cluster runs -- a small and a large cluster on one workgroup, and the
-# large one on a team of 8 -- then solved for the per-step latency, the
-# per-group pair rate and the extra per-step cost of a multi-group team.
+# Ensemble team-planning model (nbody_ensemble_config), fitted on a
+# representative launch: a synthetic ensemble drawn like the workload is run,
+# the per-cluster wall times the kernel records are fitted by least squares
+# (per-step latency and effective pair rate of a group on single-group
+# clusters, the team cost b0 + b1 g on multi-group ones, the block-step count
+# law c N^p on all), the teams are re-planned with the fitted model, and the
+# fastest of the measured launches is kept, for 2 and 3 groups per CU.
 
-def _ens_single(n, seed, max_team, groups_per_cu, t_end, dt_max, mode):
+def _ens_mixed_inputs():
+    # 256 clusters drawn like the ensemble workload (log-uniform N in
+    # [256, 8192], eps = N^(-1/3)/16) but from other seeds
     import numpy as np
-    from workloads.plummer import plummer
-    from . import ensemble_run, ensemble_set
-    p, v, m = plummer(n, seed)
-    P, V, M = (torch.from_numpy(a).cuda() for a in (p, v, m))
-    eps2 = (n ** (-1.0 / 3.0) / 16.0) ** 2
-    off = np.array([0, n], dtype=np.int64)
-    ensemble_set(groups_per_cu=groups_per_cu, max_team=max_team)
-    ensemble_run(P, V, M, off, [eps2], t_end, dt_max=dt_max, mode=mode)  # warm-up
+    from workloads.plummer import cluster_sizes, plummer
+    sizes = cluster_sizes(256, 256, 8192, 4242)
+    parts = [plummer(int(n), 5000 + k) for k, n in enumerate(sizes)]
+    P = torch.from_numpy(np.concatenate([q[0] for q in parts], axis=1)).cuda()
+    V = torch.from_numpy(np.concatenate([q[1] for q in parts], axis=1)).cuda()
+    M = torch.from_numpy(np.concatenate([q[2] for q in parts])).cuda()
+    off = np.concatenate([[0], np.cumsum(sizes)]).astype(np.int64)
+    eps2 = (sizes.astype(np.float64) ** (-1.0 / 3.0) / 16.0) ** 2
+    return sizes, P, V, M, off, eps2
+
+
+def _ens_mixed_run(inp, mode, t_end, dt_max):
+    """Time one launch; return (seconds, per-cluster rows (sec, g, N, steps, inter))."""
+    from . import ensemble_run, ensemble_timing
+    sizes, P, V, M, off, eps2 = inp
+    ensemble_run(P, V, M, off, eps2, t_end, dt_max=dt_max, mode=mode)
     torch.cuda.synchronize()
     e0 = torch.cuda.Event(enable_timing=True)
     e1 = torch.cuda.Event(enable_timing=True)
     e0.record()
-    out = ensemble_run(P, V, M, off, [eps2], t_end, dt_max=dt_max, mode=mode)
+    out = ensemble_run(P, V, M, off, eps2, t_end, dt_max=dt_max, mode=mode)
     e1.record()
     torch.cuda.synchronize()
-    return e0.elapsed_time(e1) * 1e-3, out["steps"][0], out["interactions"][0]
+    sec, grp = ensemble_timing(len(sizes))
+    rows = list(zip(sec, grp, [int(n) for n in sizes], out["steps"], out["interactions"]))
+    return e0.elapsed_time(e1) * 1e-3, rows
 
 
-def calibrate_ensemble(mode="fp32", t_end=1.0 / 16, dt_max=1.0 / 16, log=None):
+def _fit_model(rows, cfg, t_end):
+    """Least-squares fit of the time model to measured clusters of one launch."""
+    import numpy as np
+    r = np.array(rows, dtype=np.float64)
+    sec, g, n, st, it = r.T
+    new = dict(cfg)
+    one = g == 1
+    if one.sum() >= 4:
+        A = np.stack([st[one], it[one]], axis=1)
+        sol, *_ = np.linalg.lstsq(A, sec[one], rcond=None)
+        if sol[0] > 0 and sol[1] > 0:
+            new["step_us"] = sol[0] * 1e6
+            new["group_rate"] = 1.0 / sol[1]
+    many = g > 1
+    if many.sum() >= 3:
+        rest = (sec[many] - st[many] * new["step_us"] * 1e-6
+                - it[many] / (g[many] * new["group_rate"])) / st[many]
+        A = np.stack([np.ones(many.sum()), g[many]], axis=1)
+        sol, *_ = np.linalg.lstsq(A, rest, rcond=None)
+        new["barrier_us"] = max(0.0, sol[0] * 1e6)
+        new["barrier_group_us"] = max(0.0, sol[1] * 1e6)
+    ok = st > 0
+    p, logc = np.polyfit(np.log(n[ok]), np.log(st[ok] / t_end), 1)
+    new["steps_exp"], new["steps_coef"] = float(p), float(np.exp(logc))
+    return new
+
+
+def calibrate_ensemble(mode="fp32", t_end=1.0 / 16, dt_max=1.0 / 16, log=None, rounds=3):
+    """Fit the team-planning model by running a representative ensemble,
+    refitting on its per-cluster times and re-planning; keep the fastest."""
     from . import ensemble_get, ensemble_set
     saved = ensemble_get()
+    inp = _ens_mixed_inputs()
+    best = None
     try:
-        # one group: t = steps * step + interactions / rate
-        ts, ss, is_ = _ens_single(256, 91, 1, saved["groups_per_cu"], t_end, dt_max, mode)
-        tl, sl, il = _ens_single(4096, 92, 1, saved["groups_per_cu"], t_end, dt_max, mode)
-        a = [[ss, is_], [sl, il]]
-        det = a[0][0] * a[1][1] - a[0][1] * a[1][0]
-        step = (ts * a[1][1] - tl * a[0][1]) / det
-        inv_rate = (a[0][0] * tl - a[1][0] * ts) / det
-        step = max(step, 1e-6)
-        rate = 1.0 / inv_rate if inv_rate > 0 else saved["group_rate"]
-        # a team of 8 groups on the large cluster: the rest is barrier cost
-        t8, s8, i8 = _ens_single(4096, 92, 8, saved["groups_per_cu"], t_end, dt_max, mode)
-        barrier = max(0.0, (t8 - s8 * step - i8 / (8 * rate)) / s8)
-        cfg = dict(saved, step_us=step * 1e6, barrier_us=barrier * 1e6, group_rate=rate)
+        for gpc in (2, 3):
+            cfg = dict(saved, groups_per_cu=gpc)
+            for k in range(rounds):
+                ensemble_set(**cfg)
+                secs, rows = _ens_mixed_run(inp, mode, t_end, dt_max)
+                if log:
+                    log("ensemble calibration gpc=%d round %d: %.4f s" % (gpc, k, secs))
+                if best is None or secs < best[1]:
+                    best = (dict(cfg), secs)
+                cfg = _fit_model(rows, cfg, t_end)
+        cfg = best[0]
         if log:
-            log("ensemble model: step %.1f us, barrier %.1f us, group rate %.3e /s"
-                % (cfg["step_us"], cfg["barrier_us"], cfg["group_rate"]))
+            log("ensemble model: step %.1f us, barrier %.1f + %.2f g us, group rate %.3e /s, "
+                "steps %.1f N^%.3f per time unit, %d groups per CU (%.4f s)"
+                % (cfg["step_us"], cfg["barrier_us"], cfg["barrier_group_us"],
+                   cfg["group_rate"], cfg["steps_coef"], cfg["steps_exp"],
+                   cfg["groups_per_cu"], best[1]))
         return cfg
     finally:
         ensemble_set(**saved)

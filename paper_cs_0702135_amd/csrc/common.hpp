@@ -77,9 +77,11 @@ struct nbody_ctx {
     size_t adj_bytes = 0;
     void *ens = nullptr;  // ensemble tables, team scratch, predicted state
     size_t ens_bytes = 0;
-    nbody_ensemble_config ens_cfg = {2, 64, 30.0, 15.0, 2.0e9};
+    nbody_ensemble_config ens_cfg = {2, 64, 30.0, 15.0, 0.5, 2.0e9, 247.0, 0.35};
     int ens_last_grid = 0;
     int ens_last_teams = 0;
+    std::vector<double> ens_last_seconds;  // per cluster, last ensemble launch
+    std::vector<int> ens_last_groups;
     nb::StepInfo *info = nullptr;  // device
     nb::StepInfo *info_host = nullptr;  // pinned host mirror
     // block-step buffers

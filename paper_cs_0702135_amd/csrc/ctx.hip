@@ -246,8 +246,10 @@ int nbody_ensemble_set(nbody_ctx *ctx, const nbody_ensemble_config *cfg) {
     if (!ctx || !cfg) return NBODY_E_INVAL;
     if (cfg->groups_per_cu < 1 || cfg->groups_per_cu > 8 || cfg->max_team < 1 ||
         cfg->max_team > 4096 || !(cfg->step_us >= 0) || !(cfg->barrier_us >= 0) ||
+        !(cfg->barrier_group_us >= 0) || std::isinf(cfg->barrier_group_us) ||
         !(cfg->group_rate > 0) || std::isinf(cfg->step_us) || std::isinf(cfg->barrier_us) ||
-        std::isinf(cfg->group_rate))
+        std::isinf(cfg->group_rate) || !(cfg->steps_coef > 0) || !(cfg->steps_exp >= 0) ||
+        !(cfg->steps_exp < 3) || std::isinf(cfg->steps_coef))
         return fail(ctx, NBODY_E_INVAL, "nbody_ensemble_set: bad values");
     ctx->ens_cfg = *cfg;
     return NBODY_OK;
@@ -263,6 +265,19 @@ int nbody_ensemble_info(nbody_ctx *ctx, int32_t *grid, int32_t *teams) {
     if (!ctx) return NBODY_E_INVAL;
     if (grid) *grid = ctx->ens_last_grid;
     if (teams) *teams = ctx->ens_last_teams;
+    return NBODY_OK;
+}
+
+int nbody_ensemble_timing(nbody_ctx *ctx, int32_t n_clusters, double *seconds,
+                          int32_t *groups) {
+    if (!ctx) return NBODY_E_INVAL;
+    if (n_clusters != (int32_t)ctx->ens_last_seconds.size())
+        return fail(ctx, NBODY_E_INVAL, "nbody_ensemble_timing: %d clusters in the last run",
+                    (int)ctx->ens_last_seconds.size());
+    for (int c = 0; c < n_clusters; ++c) {
+        if (seconds) seconds[c] = ctx->ens_last_seconds[c];
+        if (groups) groups[c] = ctx->ens_last_groups[c];
+    }
     return NBODY_OK;
 }
 

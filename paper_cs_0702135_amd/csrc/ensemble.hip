@@ -13,13 +13,14 @@
 // raises an abort flag that every group checks, so the grid always drains.
 //
 // The host plans the teams from a time model.  A cluster of N particles
-// takes about S = 247 N^0.35 t_end block steps with blocks of 0.20 N^0.81
-// particles (the paper's fits of steps per time unit and of the mean block
-// size), so on a team of g groups it takes
-//     T(N, g) = S (step + [g > 1] barrier + 0.20 N^1.81 / (g rate))
-// where step is the fixed latency of one block step on one group, barrier
-// the extra cost of a multi-group step and rate the pair interactions per
-// second of one group (all three calibrated by the autotuner).  With at
+// takes about S = c N^p t_end block steps with blocks of 0.20 N^0.81
+// particles (the paper fits c = 247, p = 0.35 for the steps per time unit,
+// and that block size; c and p are recalibrated from measured runs), so on a
+// team of g groups it takes
+//     T(N, g) = S (step + [g > 1] (b0 + b1 g) + 0.20 N^1.81 / (g rate))
+// where step is the fixed latency of one block step on one group, b0 + b1 g
+// the extra cost of a step of a team of g groups and rate the pair
+// interactions per second of one group (all calibrated by the autotuner).  With at
 // least as many groups as clusters every cluster gets its own team and the
 // spare groups go, one at a time, to the team with the largest T (while
 // that lowers it); otherwise clusters are packed onto single-group teams,
@@ -69,8 +70,9 @@ struct EnsArgs {
     const EnsTeam *teams;
     const int32_t *wg_team, *wg_rank;
     double *scratch;
-    uint32_t *bars;  // 32 words per team: arrivals at [0], generation at [16]
+    uint32_t *bars;  // 64 arrival words per team (one per group rank)
     int64_t *steps, *inter;
+    uint64_t *clock;  // per cluster: wall clock at its start and end
     int32_t *status, *abort;
     int64_t spin_limit;  // wall-clock ticks
 };
@@ -86,46 +88,54 @@ __device__ __forceinline__ bool aborted(const int32_t *abort) {
 }
 
 // Team barrier; returns false if the launch is being aborted.
-// The groups of a team sit on different XCDs, whose L2 caches are made
-// coherent only by agent-scope release/acquire.  After the workgroup barrier
-// (every wave's stores complete), one thread issues the release (L2
-// write-back), arrives, waits by polling the generation word with relaxed
-// loads (an acquire per poll would invalidate the L2 under the groups still
-// computing on that XCD), and issues one acquire (L1/L2 invalidate) when the
-// whole team has arrived; the cache operations act for the whole CU / XCD.
-__device__ bool team_barrier(uint32_t *bar, int g, int32_t *abort, int64_t limit) {
+// Each group of a team owns one arrival word (64 words per team, one per
+// possible rank).  Arriving, thread 0 releases the group's writes at agent
+// scope (the groups of a team sit on different XCDs, whose L2 caches are
+// made coherent only by release/acquire) and stores the group's new epoch in
+// its word; wave 0 then polls all g words of the team with one coalesced
+// relaxed load per poll until every word has reached the epoch, and issues
+// one agent-scope acquire.  No read-modify-write is contended, and no
+// acquire is issued while polling (each would invalidate the L2 under the
+// groups still computing on that XCD).  Polls are bounded by a wall-clock
+// limit that raises the launch-wide abort flag.
+__device__ bool team_barrier(uint32_t *flags, int g, int rank, uint32_t &epoch, int32_t *abort,
+                             int64_t limit) {
     __shared__ int ok;
     __syncthreads();
-    if (threadIdx.x == 0) {
-        int good = 1;
-        if (g > 1) {
-            uint32_t *cnt = bar, *gen = bar + 16;
+    epoch += 1;
+    if (g > 1) {
+        if (threadIdx.x == 0) {
             __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-            const uint32_t my = __hip_atomic_load(gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            const uint32_t arrived =
-                __hip_atomic_fetch_add(cnt, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            if (arrived == (uint32_t)(g - 1)) {
-                __hip_atomic_store(cnt, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                __hip_atomic_fetch_add(gen, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-            } else {
-                const uint64_t t0 = wall_clock64();
-                while (__hip_atomic_load(gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == my) {
-                    if (aborted(abort)) {
-                        good = 0;
-                        break;
-                    }
-                    if ((int64_t)(wall_clock64() - t0) > limit) {
-                        __hip_atomic_store(abort, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                        good = 0;
-                        break;
-                    }
-                    __builtin_amdgcn_s_sleep(2);
-                }
-            }
-            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+            __hip_atomic_store(&flags[rank], epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         }
-        if (aborted(abort)) good = 0;
-        ok = good;
+        if (threadIdx.x < 64) {
+            const int lane = threadIdx.x;
+            const uint64_t t0 = wall_clock64();
+            int good = 1;
+            for (;;) {
+                const uint32_t v = lane < g ? __hip_atomic_load(&flags[lane], __ATOMIC_RELAXED,
+                                                                __HIP_MEMORY_SCOPE_AGENT)
+                                            : epoch;
+                if (__ballot((int32_t)(v - epoch) < 0) == 0ull) break;
+                if (aborted(abort)) {
+                    good = 0;
+                    break;
+                }
+                if ((int64_t)(wall_clock64() - t0) > limit) {
+                    if (lane == 0)
+                        __hip_atomic_store(abort, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    good = 0;
+                    break;
+                }
+                __builtin_amdgcn_s_sleep(1);
+            }
+            if (lane == 0) {
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+                ok = good && !aborted(abort);
+            }
+        }
+    } else if (threadIdx.x == 0) {
+        ok = !aborted(abort);
     }
     __syncthreads();
     return ok != 0;
@@ -142,31 +152,48 @@ __device__ __forceinline__ void ds_fold(float &hi, float &lo, float x, bool ds) 
     }
 }
 
-// Pair sums of one work item (64 i-slots x a j range) of a cluster.
+// Pair sums of one work item (64 * EIT i-slots x a j range) of a cluster.
 // src_x/src_v: state to read (component stride nt); i-slot s is particle
-// act[s] (or s when act is null).  Result: 7 float64 per slot in wave 0.
+// act[s] (or s when act is null); lane l holds slots ib*64*EIT + t*64 + l.
+// Result: 7 float64 per slot and t in wave 0.
+constexpr int EIT = 2;
+
 template <bool DS>
 __device__ void ens_pair_item(const EnsArgs &A, const double *src_x, const double *src_v,
                               int64_t base, int n, float eps2, const int32_t *act, int n_i,
-                              int64_t ib, int j0, int j1, TileRec *tile, double (*red)[7][64],
-                              double tot[7]) {
+                              int64_t ib, int j0, int j1, TileRec *tile,
+                              double (*red)[7 * EIT][64], double tot[EIT][7]) {
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;
     const int64_t nt = A.nt;
-    const int slot = (int)(ib * 64 + lane);
-    const int sl = slot < n_i ? slot : n_i - 1;
-    const int ip = act ? act[sl] : sl;  // cluster-local index
-    const double xi = src_x[base + ip], yi = src_x[nt + base + ip], zi = src_x[2 * nt + base + ip];
-    const double ui = src_v[base + ip], vi = src_v[nt + base + ip], wi = src_v[2 * nt + base + ip];
-    int lo = ip, hi = ip;
+    double xi[EIT], yi[EIT], zi[EIT], ui[EIT], vi[EIT], wi[EIT];
+    int ip[EIT];
+    int lo = 0x7fffffff, hi = -1;
+#pragma unroll
+    for (int t = 0; t < EIT; ++t) {
+        const int slot = (int)(ib * 64 * EIT + t * 64 + lane);
+        const int sl = slot < n_i ? slot : n_i - 1;
+        ip[t] = act ? act[sl] : sl;  // cluster-local index
+        const int64_t q = base + ip[t];
+        xi[t] = src_x[q];
+        yi[t] = src_x[nt + q];
+        zi[t] = src_x[2 * nt + q];
+        ui[t] = src_v[q];
+        vi[t] = src_v[nt + q];
+        wi[t] = src_v[2 * nt + q];
+        lo = min(lo, ip[t]);
+        hi = max(hi, ip[t]);
+    }
 #pragma unroll
     for (int o = 32; o >= 1; o >>= 1) {
         lo = min(lo, __shfl_xor(lo, o, 64));
         hi = max(hi, __shfl_xor(hi, o, 64));
     }
-    float sh[7], sl7[7];
+    float sh[EIT][7], sl7[EIT][7];
 #pragma unroll
-    for (int c = 0; c < 7; ++c) sh[c] = sl7[c] = 0.0f;
+    for (int t = 0; t < EIT; ++t)
+#pragma unroll
+        for (int c = 0; c < 7; ++c) sh[t][c] = sl7[t][c] = 0.0f;
     for (int jt = j0; jt < j1; jt += ETILE) {
         const int cnt = min(ETILE, j1 - jt);
         __syncthreads();
@@ -184,50 +211,71 @@ __device__ void ens_pair_item(const EnsArgs &A, const double *src_x, const doubl
         }
         __syncthreads();
         const int r0 = wave * 64, r1 = min(cnt, r0 + 64);
-        float in[7];
+        float in[EIT][7];
 #pragma unroll
-        for (int c = 0; c < 7; ++c) in[c] = 0.0f;
-        const bool mask = (jt + r0 <= hi) && (jt + r1 > lo);
-        for (int r = r0; r < r1; ++r) {
-            const TileRec &R = tile[r];
-            const float dx = (float)(R.x - xi), dy = (float)(R.y - yi), dz = (float)(R.z - zi);
-            const float du = (float)(R.u - ui), dv = (float)(R.v - vi), dw = (float)(R.w - wi);
-            float s2 = fmaf(dz, dz, fmaf(dy, dy, fmaf(dx, dx, eps2)));
-            float mj = R.m;
-            if (mask) {
-                const bool self = (jt + r == ip);
-                s2 = self ? 1.0f : s2;
-                mj = self ? 0.0f : mj;
+        for (int t = 0; t < EIT; ++t)
+#pragma unroll
+            for (int c = 0; c < 7; ++c) in[t][c] = 0.0f;
+        auto body = [&](const TileRec &R, const int j, const bool mask)
+            __attribute__((always_inline)) {
+#pragma unroll
+            for (int t = 0; t < EIT; ++t) {
+                const float dx = (float)(R.x - xi[t]), dy = (float)(R.y - yi[t]);
+                const float dz = (float)(R.z - zi[t]);
+                const float du = (float)(R.u - ui[t]), dv = (float)(R.v - vi[t]);
+                const float dw = (float)(R.w - wi[t]);
+                float s2 = fmaf(dz, dz, fmaf(dy, dy, fmaf(dx, dx, eps2)));
+                float mj = R.m;
+                if (mask) {
+                    const bool self = (j == ip[t]);
+                    s2 = self ? 1.0f : s2;
+                    mj = self ? 0.0f : mj;
+                }
+                const float rv = fmaf(dz, dw, fmaf(dy, dv, dx * du));
+                const float rinv = __builtin_amdgcn_rsqf(s2);
+                const float rinv2 = rinv * rinv;
+                const float mr1 = mj * rinv;
+                const float mr3 = mr1 * rinv2;
+                const float w3 = (rv * rinv2) * -3.0f;
+                in[t][0] = fmaf(mr3, dx, in[t][0]);
+                in[t][1] = fmaf(mr3, dy, in[t][1]);
+                in[t][2] = fmaf(mr3, dz, in[t][2]);
+                in[t][3] = fmaf(mr3, fmaf(w3, dx, du), in[t][3]);
+                in[t][4] = fmaf(mr3, fmaf(w3, dy, dv), in[t][4]);
+                in[t][5] = fmaf(mr3, fmaf(w3, dz, dw), in[t][5]);
+                in[t][6] = fmaf(mj, rinv, in[t][6]);
             }
-            const float rv = fmaf(dz, dw, fmaf(dy, dv, dx * du));
-            const float rinv = __builtin_amdgcn_rsqf(s2);
-            const float rinv2 = rinv * rinv;
-            const float mr1 = mj * rinv;
-            const float mr3 = mr1 * rinv2;
-            const float w3 = (rv * rinv2) * -3.0f;
-            in[0] = fmaf(mr3, dx, in[0]);
-            in[1] = fmaf(mr3, dy, in[1]);
-            in[2] = fmaf(mr3, dz, in[2]);
-            in[3] = fmaf(mr3, fmaf(w3, dx, du), in[3]);
-            in[4] = fmaf(mr3, fmaf(w3, dy, dv), in[4]);
-            in[5] = fmaf(mr3, fmaf(w3, dz, dw), in[5]);
-            in[6] = fmaf(mj, rinv, in[6]);
+        };
+        if ((jt + r0 <= hi) && (jt + r1 > lo)) {
+            for (int r = r0; r < r1; ++r) body(tile[r], jt + r, true);
+        } else {
+#pragma unroll 4
+            for (int r = r0; r < r1; ++r) body(tile[r], jt + r, false);
         }
 #pragma unroll
-        for (int c = 0; c < 7; ++c) ds_fold(sh[c], sl7[c], in[c], DS);
+        for (int t = 0; t < EIT; ++t)
+#pragma unroll
+            for (int c = 0; c < 7; ++c) ds_fold(sh[t][c], sl7[t][c], in[t][c], DS);
     }
 #pragma unroll
-    for (int c = 0; c < 7; ++c) tot[c] = (double)sh[c] + (double)sl7[c];
-    tot[6] = -tot[6];
+    for (int t = 0; t < EIT; ++t) {
+#pragma unroll
+        for (int c = 0; c < 7; ++c) tot[t][c] = (double)sh[t][c] + (double)sl7[t][c];
+        tot[t][6] = -tot[t][6];
+    }
     __syncthreads();
     if (wave > 0)
 #pragma unroll
-        for (int c = 0; c < 7; ++c) red[wave - 1][c][lane] = tot[c];
+        for (int t = 0; t < EIT; ++t)
+#pragma unroll
+            for (int c = 0; c < 7; ++c) red[wave - 1][t * 7 + c][lane] = tot[t][c];
     __syncthreads();
     if (wave == 0)
         for (int w = 1; w < EW; ++w)
 #pragma unroll
-            for (int c = 0; c < 7; ++c) tot[c] += red[w - 1][c][lane];
+            for (int t = 0; t < EIT; ++t)
+#pragma unroll
+                for (int c = 0; c < 7; ++c) tot[t][c] += red[w - 1][t * 7 + c][lane];
 }
 
 // Pair sums of a whole active block of a cluster, spread over the team:
@@ -236,8 +284,9 @@ template <bool DS>
 __device__ bool ens_pairs(const EnsArgs &A, const double *src_x, const double *src_v,
                           int64_t base, int n, float eps2, const int32_t *act, int n_i, int g,
                           int rank, int s_max, int n_max, double *anew, double *knew,
-                          double *part, uint32_t *bar, TileRec *tile, double (*red)[7][64]) {
-    const int64_t nb = (n_i + 63) / 64;
+                          double *part, uint32_t *bar, uint32_t &epoch, TileRec *tile,
+                          double (*red)[7 * EIT][64]) {
+    const int64_t nb = (n_i + 64 * EIT - 1) / (64 * EIT);
     int64_t S = (g + nb - 1) / nb;  // about one item per group
     int64_t smax = max(1, n / ETILE);
     if (smax > s_max) smax = s_max;
@@ -249,24 +298,28 @@ __device__ bool ens_pairs(const EnsArgs &A, const double *src_x, const double *s
     for (int64_t it = rank; it < items; it += g) {
         const int64_t ib = it % nb, sp = it / nb;
         const int j0 = (int)(sp * jchunk), j1 = min(n, j0 + jchunk);
-        double tot[7];
+        double tot[EIT][7];
         ens_pair_item<DS>(A, src_x, src_v, base, n, eps2, act, n_i, ib, j0, j1, tile, red, tot);
-        const int slot = (int)(ib * 64 + lane);
-        if ((threadIdx.x >> 6) == 0 && slot < n_i) {
-            if (S == 1) {
+        if ((threadIdx.x >> 6) == 0) {
 #pragma unroll
-                for (int c = 0; c < 3; ++c) {
-                    anew[c * n_max + slot] = tot[c];
-                    knew[c * n_max + slot] = tot[3 + c];
+            for (int t = 0; t < EIT; ++t) {
+                const int slot = (int)(ib * 64 * EIT + t * 64 + lane);
+                if (slot >= n_i) continue;
+                if (S == 1) {
+#pragma unroll
+                    for (int c = 0; c < 3; ++c) {
+                        anew[c * n_max + slot] = tot[t][c];
+                        knew[c * n_max + slot] = tot[t][3 + c];
+                    }
+                } else {
+#pragma unroll
+                    for (int c = 0; c < 6; ++c) part[(sp * 6 + c) * n_max + slot] = tot[t][c];
                 }
-            } else {
-#pragma unroll
-                for (int c = 0; c < 6; ++c) part[(sp * 6 + c) * n_max + slot] = tot[c];
             }
         }
     }
     if (S > 1) {
-        if (!team_barrier(bar, g, A.abort, A.spin_limit)) return false;
+        if (!team_barrier(bar, g, rank, epoch, A.abort, A.spin_limit)) return false;
         const int64_t total = 6 * (int64_t)n_i;
         for (int64_t e = (int64_t)rank * ETH + threadIdx.x; e < total; e += (int64_t)g * ETH) {
             const int c = (int)(e / n_i), s = (int)(e - (int64_t)c * n_i);
@@ -278,20 +331,21 @@ __device__ bool ens_pairs(const EnsArgs &A, const double *src_x, const double *s
                 knew[(c - 3) * n_max + s] = acc;
         }
     }
-    return team_barrier(bar, g, A.abort, A.spin_limit);
+    return team_barrier(bar, g, rank, epoch, A.abort, A.spin_limit);
 }
 
 template <bool DS>
 __global__ __launch_bounds__(ETH) void ensemble_kernel(const EnsArgs A) {
     __shared__ TileRec tile[ETILE];
-    __shared__ double red[EW - 1][7][64];
+    __shared__ double red[EW - 1][7 * EIT][64];
     __shared__ double smin[ETH];
     __shared__ int scount[ETH];
     const int team = A.wg_team[blockIdx.x];
     const int rank = A.wg_rank[blockIdx.x];
     const EnsTeam T = A.teams[team];
     const int g = T.size;
-    uint32_t *bar = A.bars + 32 * (int64_t)team;
+    uint32_t *bar = A.bars + 64 * (int64_t)team;  // arrival words of the team
+    uint32_t epoch = 0;
     double *scr = A.scratch + T.scratch_off;
     const int n_max = T.n_max;
     // scratch layout (doubles): pmin[g] | pcnt[g] | active[n_max] (int32) |
@@ -313,10 +367,11 @@ __global__ __launch_bounds__(ETH) void ensemble_kernel(const EnsArgs A) {
         const float eps2 = C.eps2;
         const int per = (n + g - 1) / g;
         const int p0 = min(n, rank * per), p1 = min(n, p0 + per);
+        if (rank == 0 && tid == 0) A.clock[2 * c] = wall_clock64();
 
         // ---- initialisation: pair sums of every particle, initial steps
         if (!ens_pairs<DS>(A, A.x, A.v, base, n, eps2, nullptr, n, g, rank, T.s_max, n_max, anew,
-                           knew, part, bar, tile, red))
+                           knew, part, bar, epoch, tile, red))
             return;
         for (int i = p0 + tid; i < p1; i += ETH) {
             const int64_t q = base + i;
@@ -330,7 +385,7 @@ __global__ __launch_bounds__(ETH) void ensemble_kernel(const EnsArgs A) {
             A.dt[q] = initial_dt_one(q, nt, 0.0, A.a, A.k, A.eta_s, A.dt_max, A.dt_min, &st);
             if (st) atomicOr(A.status, st);
         }
-        if (!team_barrier(bar, g, A.abort, A.spin_limit)) return;
+        if (!team_barrier(bar, g, rank, epoch, A.abort, A.spin_limit)) return;
 
         int64_t my_steps = 0, my_inter = 0;
         for (;;) {
@@ -344,7 +399,7 @@ __global__ __launch_bounds__(ETH) void ensemble_kernel(const EnsArgs A) {
                 __syncthreads();
             }
             if (tid == 0) pmin[rank] = smin[0];
-            if (!team_barrier(bar, g, A.abort, A.spin_limit)) return;
+            if (!team_barrier(bar, g, rank, epoch, A.abort, A.spin_limit)) return;
             double tn = INFINITY;
             for (int r = 0; r < g; ++r)
                 tn = fmin(tn, __hip_atomic_load(&pmin[r], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
@@ -360,7 +415,7 @@ __global__ __launch_bounds__(ETH) void ensemble_kernel(const EnsArgs A) {
                 __syncthreads();
             }
             if (tid == 0) pcnt[rank] = scount[0];
-            if (!team_barrier(bar, g, A.abort, A.spin_limit)) return;
+            if (!team_barrier(bar, g, rank, epoch, A.abort, A.spin_limit)) return;
             int64_t before = 0, n_i = 0;
             for (int r = 0; r < g; ++r) {
                 const int64_t cr = __hip_atomic_load(&pcnt[r], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -401,11 +456,11 @@ __global__ __launch_bounds__(ETH) void ensemble_kernel(const EnsArgs A) {
                     off += tot;
                 }
             }
-            if (!team_barrier(bar, g, A.abort, A.spin_limit)) return;
+            if (!team_barrier(bar, g, rank, epoch, A.abort, A.spin_limit)) return;
 
             // ---- pair sums of the block at the predicted state
             if (!ens_pairs<DS>(A, A.xp, A.vp, base, n, eps2, act, (int)n_i, g, rank, T.s_max, n_max,
-                               anew, knew, part, bar, tile, red))
+                               anew, knew, part, bar, epoch, tile, red))
                 return;
 
             // ---- correct the block
@@ -425,25 +480,27 @@ __global__ __launch_bounds__(ETH) void ensemble_kernel(const EnsArgs A) {
             }
             my_steps += 1;
             my_inter += n_i * n;
-            if (!team_barrier(bar, g, A.abort, A.spin_limit)) return;
+            if (!team_barrier(bar, g, rank, epoch, A.abort, A.spin_limit)) return;
         }
         if (rank == 0 && tid == 0) {
             A.steps[c] = my_steps;
             A.inter[c] = my_inter;
+            A.clock[2 * c + 1] = wall_clock64();
         }
         // the next cluster's initialisation writes anew/knew and act: make
         // sure every group of the team is past this cluster
-        if (!team_barrier(bar, g, A.abort, A.spin_limit)) return;
+        if (!team_barrier(bar, g, rank, epoch, A.abort, A.spin_limit)) return;
     }
 }
 
 __global__ void ens_clear_kernel(uint32_t *bars, int64_t nbars, int64_t *steps, int64_t *inter,
-                                 int64_t nc, int32_t *flags) {
+                                 uint64_t *clock, int64_t nc, int32_t *flags) {
     const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (i < nbars) bars[i] = 0;
     if (i < nc) {
         steps[i] = 0;
         inter[i] = 0;
+        clock[2 * i] = clock[2 * i + 1] = 0;
     }
     if (i < 2) flags[i] = 0;
 }
@@ -456,10 +513,10 @@ struct Plan {
 };
 
 struct TimeModel {
-    double step_s, barrier_s, rate, t_end;
-    double steps(double n) const { return std::max(1.0, 247.0 * std::pow(n, 0.35) * t_end); }
+    double step_s, barrier_s, barrier_g_s, rate, t_end, coef, expo;
+    double steps(double n) const { return std::max(1.0, coef * std::pow(n, expo) * t_end); }
     double time(double n, int g) const {
-        const double per_step = step_s + (g > 1 ? barrier_s : 0.0) +
+        const double per_step = step_s + (g > 1 ? barrier_s + barrier_g_s * g : 0.0) +
                                 0.20 * std::pow(n, 1.81) / ((double)g * rate);
         return steps(n) * per_step;
     }
@@ -582,8 +639,9 @@ extern "C" int nbody_ensemble_run(nbody_ctx *ctx, const nbody_ensemble *e, doubl
     if (per_cu < 1) return fail(ctx, NBODY_E_DEVICE, "ensemble kernel does not fit a CU");
     const int G = per_cu * ctx->cus;
     const nbody_ensemble_config &cf = ctx->ens_cfg;
-    TimeModel M{cf.step_us * 1e-6, cf.barrier_us * 1e-6, cf.group_rate, t_end > 0 ? t_end : 0.0};
-    Plan P = plan_teams(sizes, G, cf.max_team, M);
+    TimeModel M{cf.step_us * 1e-6,   cf.barrier_us * 1e-6, cf.barrier_group_us * 1e-6,
+                cf.group_rate,       t_end > 0 ? t_end : 0.0, cf.steps_coef, cf.steps_exp};
+    Plan P = plan_teams(sizes, G, std::min(cf.max_team, 64), M);
     const int grid = (int)P.wg_team.size();
     const int nteams = (int)P.teams.size();
 
@@ -594,9 +652,11 @@ extern "C" int nbody_ensemble_run(nbody_ctx *ctx, const nbody_ensemble *e, doubl
     auto al = [](size_t b) { return (b + 255) & ~size_t(255); };
     const size_t b_cl = al(sizeof(EnsCluster) * nc), b_ord = al(4 * P.order.size()),
                  b_tm = al(sizeof(EnsTeam) * nteams), b_wg = al(4 * (size_t)grid),
-                 b_bar = al(4 * 32 * (size_t)nteams), b_cnt = al(8 * (size_t)nc),
+                 b_bar = al(4 * 64 * (size_t)nteams), b_cnt = al(8 * (size_t)nc),
+                 b_clk = al(16 * (size_t)nc),
                  b_fl = al(8), b_scr = al(8 * (size_t)P.scratch), b_st = al(8 * 3 * (size_t)nt);
-    const size_t total = b_cl + b_ord + b_tm + 2 * b_wg + b_bar + 2 * b_cnt + b_fl + b_scr + 2 * b_st;
+    const size_t total =
+        b_cl + b_ord + b_tm + 2 * b_wg + b_bar + 2 * b_cnt + b_clk + b_fl + b_scr + 2 * b_st;
     NB_TRY(ensure(ctx, &ctx->ens, &ctx->ens_bytes, total));
     char *p = (char *)ctx->ens;
     EnsCluster *d_cl = (EnsCluster *)p; p += b_cl;
@@ -607,6 +667,7 @@ extern "C" int nbody_ensemble_run(nbody_ctx *ctx, const nbody_ensemble *e, doubl
     uint32_t *d_bar = (uint32_t *)p; p += b_bar;
     int64_t *d_steps = (int64_t *)p; p += b_cnt;
     int64_t *d_inter = (int64_t *)p; p += b_cnt;
+    uint64_t *d_clock = (uint64_t *)p; p += b_clk;
     int32_t *d_flags = (int32_t *)p; p += b_fl;
     double *d_scr = (double *)p; p += b_scr;
     double *d_xp = (double *)p; p += b_st;
@@ -617,9 +678,9 @@ extern "C" int nbody_ensemble_run(nbody_ctx *ctx, const nbody_ensemble *e, doubl
     NB_TRY(hip_check(ctx, hipMemcpyAsync(d_tm, P.teams.data(), sizeof(EnsTeam) * nteams, hipMemcpyHostToDevice, ctx->stream), "copy"));
     NB_TRY(hip_check(ctx, hipMemcpyAsync(d_wgt, P.wg_team.data(), 4 * (size_t)grid, hipMemcpyHostToDevice, ctx->stream), "copy"));
     NB_TRY(hip_check(ctx, hipMemcpyAsync(d_wgr, P.wg_rank.data(), 4 * (size_t)grid, hipMemcpyHostToDevice, ctx->stream), "copy"));
-    const int64_t nclr = std::max<int64_t>(32 * (int64_t)nteams, nc) + 2;
+    const int64_t nclr = std::max<int64_t>(64 * (int64_t)nteams, nc) + 2;
     ens_clear_kernel<<<(unsigned)((nclr + 255) / 256), 256, 0, ctx->stream>>>(
-        d_bar, 32 * (int64_t)nteams, d_steps, d_inter, nc, d_flags);
+        d_bar, 64 * (int64_t)nteams, d_steps, d_inter, d_clock, nc, d_flags);
     NB_TRY(hip_check(ctx, hipGetLastError(), "ens_clear_kernel"));
 
     int wclk_khz = 0;
@@ -635,7 +696,7 @@ extern "C" int nbody_ensemble_run(nbody_ctx *ctx, const nbody_ensemble *e, doubl
     A.eta = e->eta; A.eta_s = e->eta_s; A.dt_max = e->dt_max; A.dt_min = e->dt_min;
     A.t_end = t_end;
     A.cl = d_cl; A.cl_order = d_ord; A.teams = d_tm; A.wg_team = d_wgt; A.wg_rank = d_wgr;
-    A.scratch = d_scr; A.bars = d_bar; A.steps = d_steps; A.inter = d_inter;
+    A.scratch = d_scr; A.bars = d_bar; A.steps = d_steps; A.inter = d_inter; A.clock = d_clock;
     A.status = d_flags; A.abort = d_flags + 1;
     A.spin_limit = (int64_t)wclk_khz * 1000 * 20;  // 20 s of wall clock per barrier wait
     void *args[] = {&A};
@@ -643,9 +704,11 @@ extern "C" int nbody_ensemble_run(nbody_ctx *ctx, const nbody_ensemble *e, doubl
                      "ensemble_kernel (cooperative launch)"));
     int32_t hflags[2] = {0, 0};
     std::vector<int64_t> hs(nc), hi(nc);
+    std::vector<uint64_t> hclk(2 * (size_t)nc);
     NB_TRY(hip_check(ctx, hipMemcpyAsync(hflags, d_flags, 8, hipMemcpyDeviceToHost, ctx->stream), "copy"));
     NB_TRY(hip_check(ctx, hipMemcpyAsync(hs.data(), d_steps, 8 * (size_t)nc, hipMemcpyDeviceToHost, ctx->stream), "copy"));
     NB_TRY(hip_check(ctx, hipMemcpyAsync(hi.data(), d_inter, 8 * (size_t)nc, hipMemcpyDeviceToHost, ctx->stream), "copy"));
+    NB_TRY(hip_check(ctx, hipMemcpyAsync(hclk.data(), d_clock, 16 * (size_t)nc, hipMemcpyDeviceToHost, ctx->stream), "copy"));
     NB_TRY(hip_check(ctx, hipStreamSynchronize(ctx->stream), "sync"));
     if (steps)
         for (int c = 0; c < nc; ++c) steps[c] = hs[c];
@@ -653,6 +716,12 @@ extern "C" int nbody_ensemble_run(nbody_ctx *ctx, const nbody_ensemble *e, doubl
         for (int c = 0; c < nc; ++c) interactions[c] = hi[c];
     ctx->ens_last_grid = grid;
     ctx->ens_last_teams = nteams;
+    ctx->ens_last_seconds.assign(nc, 0.0);
+    ctx->ens_last_groups.assign(nc, 0);
+    for (int c = 0; c < nc; ++c)
+        ctx->ens_last_seconds[c] = (double)(hclk[2 * c + 1] - hclk[2 * c]) / ((double)wclk_khz * 1e3);
+    for (const EnsTeam &T : P.teams)
+        for (int q = T.cl_begin; q < T.cl_end; ++q) ctx->ens_last_groups[P.order[q]] = T.size;
     if (hflags[1]) return fail(ctx, NBODY_E_DEVICE, "ensemble: a team barrier timed out");
     if (hflags[0] & ST_NONFINITE) return fail(ctx, NBODY_E_NONFINITE, "ensemble: non-finite value");
     if (hflags[0] & ST_RANGE) return fail(ctx, NBODY_E_RANGE, "ensemble: time step below dt_min");
