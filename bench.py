@@ -178,6 +178,24 @@ def main():
         e1.record()
         torch.cuda.synchronize()
         aux["force_only_%s_interactions_per_s" % other] = inter_step / (e0.elapsed_time(e1) * 1e-3)
+        # force-only sweep at N = 2^20 over active-block sizes, both accumulations
+        from workloads.plummer import random_active_set
+        sweep = {}
+        for n_i in cfg.extra["n_i"]:
+            idx = None if n_i == n else torch.from_numpy(
+                random_active_set(n, n_i, cfg.seed + n_i)).cuda()
+            reps = max(1, int(3e10 // (n_i * (n - 1))))
+            for md in ("fp32", "ds"):
+                nb.force(P, V, M, eps2, idx, md)
+                torch.cuda.synchronize()
+                e0.record()
+                for _ in range(reps):
+                    nb.force(P, V, M, eps2, idx, md)
+                e1.record()
+                torch.cuda.synchronize()
+                sweep["%s_n_i_%d" % (md, n_i)] = reps * n_i * (n - 1.0) / (
+                    e0.elapsed_time(e1) * 1e-3)
+        aux["plummer1m_force_sweep_interactions_per_s"] = sweep
         # energy drift of the block-step integrator, Plummer N=1024 to t=1/4
         # (built-in shapes: the tuned table above is for N = 2^20)
         nb.tune_clear()
@@ -194,6 +212,32 @@ def main():
         aux["plummer1k_energy_drift_per_time_unit"] = abs((e_1 - e_0) / e_0) / c1.t_end
         aux["plummer1k_block_steps"] = steps1
         aux["plummer1k_ms_per_block_step"] = (tb - ta) / max(1, steps1) * 1e3
+
+        # Plummer N=65536, eps=1/1024: full-N force-only throughput, then the
+        # block-step run to t=1/8 (wall time, steps, energy drift)
+        c2 = CONFIGS["plummer64k"]
+        p2, v2, m2 = (torch.from_numpy(a).cuda() for a in plummer(c2.n, c2.seed))
+        nb.force(p2, v2, m2, c2.eps2, None, args.mode)
+        torch.cuda.synchronize()
+        e0.record()
+        for _ in range(5):
+            nb.force(p2, v2, m2, c2.eps2, None, args.mode)
+        e1.record()
+        torch.cuda.synchronize()
+        aux["plummer64k_force_only_interactions_per_s"] = 5 * c2.n * (c2.n - 1.0) / (
+            e0.elapsed_time(e1) * 1e-3)
+        s2 = nb.System(p2, v2, m2, c2.eps2, eta=c2.eta, dt_max=c2.dt_max, mode=args.mode)
+        e_0 = s2.energy()
+        torch.cuda.synchronize()
+        ta = time.perf_counter()
+        steps2 = s2.run(c2.t_end)
+        torch.cuda.synchronize()
+        tb = time.perf_counter()
+        e_1 = s2.energy()
+        aux["plummer64k_run_seconds"] = tb - ta
+        aux["plummer64k_block_steps"] = steps2
+        aux["plummer64k_run_interactions_per_s"] = s2.interactions / (tb - ta)
+        aux["plummer64k_energy_drift_per_time_unit"] = abs((e_1 - e_0) / e_0) / c2.t_end
 
         # batched ensemble: 256 clusters, N log-uniform in [256, 8192], to t = 1/16,
         # one persistent launch (inputs resident before timing; second run timed)
@@ -218,6 +262,21 @@ def main():
         aux["ensemble256_interactions_per_s"] = float(sum(res["interactions"])) / (tb - ta)
         aux["ensemble256_block_steps"] = int(sum(res["steps"]))
         aux["ensemble256_grid_teams"] = [grid, teams]
+        # ablation: the same clusters integrated one after the other, each
+        # with the single-system block-step driver (several launches per step)
+        ta = time.perf_counter()
+        abl_inter = 0
+        for c in range(len(sizes)):
+            lo_, hi_ = int(off[c]), int(off[c + 1])
+            sc = nb.System(EP[:, lo_:hi_].contiguous(), EV[:, lo_:hi_].contiguous(),
+                           EM[lo_:hi_].contiguous(), float(eps_c[c]) ** 2,
+                           eta=ce.eta, dt_max=ce.dt_max, mode=args.mode)
+            sc.run(ce.t_end)
+            abl_inter += sc.interactions
+        torch.cuda.synchronize()
+        tb = time.perf_counter()
+        aux["ensemble256_per_cluster_driver_seconds"] = tb - ta
+        aux["ensemble256_per_cluster_driver_interactions_per_s"] = abl_inter / (tb - ta)
 
         # differentiable run: N = 16384, eps = 1/512, 64 shared steps of 1/512,
         # checkpoints every 8 steps; forward + backward through the HIP adjoint
@@ -240,6 +299,17 @@ def main():
         torch.cuda.synchronize()
         tb = time.perf_counter()
         aux["grad16k_forward_backward_seconds"] = tb - ta
+        # adjoint pair kernel alone on the N=16384 state (both roles of every pair)
+        gb = torch.ones_like(GP)
+        nb.force_adjoint(GP, GV, GM, cg.eps2, gb, gb)
+        torch.cuda.synchronize()
+        e0.record()
+        for _ in range(5):
+            nb.force_adjoint(GP, GV, GM, cg.eps2, gb, gb)
+        e1.record()
+        torch.cuda.synchronize()
+        aux["grad16k_adjoint_pairs_per_s"] = 5 * cg.n * (cg.n - 1.0) / (
+            e0.elapsed_time(e1) * 1e-3)
         out["aux"] = aux
 
     if not args.no_cpu:

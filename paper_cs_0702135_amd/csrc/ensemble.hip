@@ -5,12 +5,11 @@
 // groups are partitioned into teams; a team owns a list of clusters and
 // integrates them one after the other, each from initialisation (pair sums
 // of every particle, initial steps) to t_end.  Within a team, each phase of
-// a block step -- minimum of t + dt, compaction of the active block,
-// prediction, pair sums, split reduction, correction -- is spread over the
-// team's groups and closed by a team barrier (an arrival counter and a
-// generation word in global memory, with agent-scope release/acquire).
-// Barrier waits are bounded by a wall-clock limit: if one expires the launch
-// raises an abort flag that every group checks, so the grid always drains.
+// a block step (block selection, pair sums, split reduction, correction) is
+// spread over the team's groups and closed by a team barrier (one arrival
+// word per group in global memory, agent-scope release/acquire).  Barrier
+// waits are bounded by a wall-clock limit: if one expires the launch raises
+// an abort flag that every group checks, so the grid always drains.
 //
 // The host plans the teams from a time model.  A cluster of N particles
 // takes about S = c N^p t_end block steps with blocks of 0.20 N^0.81
@@ -27,10 +26,10 @@
 // longest first onto the least-loaded team.
 //
 // The j particles of a pair-sum pass are staged through LDS in tiles (the
-// predicted state is written during this launch, so it cannot be read
-// through the scalar cache as in the standalone kernel); the four waves of a
-// group share one tile, each taking a quarter of it for the group's 64
-// i-particles, and their sums are combined in float64 in wave order.
+// state is rewritten during this launch, so it cannot be read through the
+// scalar cache as in the standalone kernel); the four waves of a group
+// share one tile, each taking a quarter of it for the group's 64 * EIT
+// block slots, and their sums are combined in float64 in wave order.
 #include <algorithm>
 #include <cmath>
 #include <numeric>
@@ -63,7 +62,6 @@ struct EnsArgs {
     int64_t nt;  // particles in the ensemble (component stride)
     double *t, *dt, *x, *v, *a, *k;
     const double *m;
-    double *xp, *vp;
     double eta, eta_s, dt_max, dt_min, t_end;
     const EnsCluster *cl;
     const int32_t *cl_order;
@@ -152,74 +150,165 @@ __device__ __forceinline__ void ds_fold(float &hi, float &lo, float x, bool ds) 
     }
 }
 
-// Pair sums of one work item (64 * EIT i-slots x a j range) of a cluster.
-// src_x/src_v: state to read (component stride nt); i-slot s is particle
-// act[s] (or s when act is null); lane l holds slots ib*64*EIT + t*64 + l.
-// Result: 7 float64 per slot and t in wave 0.
-constexpr int EIT = 2;
+// Members of an active block.  Each group of a team compacts the members in
+// its own slice [p0(r), p1(r)) of the cluster, ascending, to act[p0(r)...];
+// pre[r] (in LDS) counts the members of the slices of groups 0..r-1, so block
+// slot s belongs to the group r with pre[r] <= s < pre[r + 1].  A null act
+// stands for the whole cluster in index order.
+struct Block {
+    const int32_t *act;
+    const int *pre;  // g + 1 entries
+    int g, per, n;
+};
 
-template <bool DS>
-__device__ void ens_pair_item(const EnsArgs &A, const double *src_x, const double *src_v,
-                              int64_t base, int n, float eps2, const int32_t *act, int n_i,
-                              int64_t ib, int j0, int j1, TileRec *tile,
-                              double (*red)[7 * EIT][64], double tot[EIT][7]) {
-    const int lane = threadIdx.x & 63;
-    const int wave = threadIdx.x >> 6;
+__device__ __forceinline__ int block_member(const Block &B, int s) {
+    if (!B.act) return s;
+    int lo = 0, hi = B.g;
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (B.pre[mid] <= s)
+            lo = mid;
+        else
+            hi = mid;
+    }
+    return B.act[min(B.n, lo * B.per) + (s - B.pre[lo])];
+}
+
+// State of one particle as loaded, before prediction.
+struct Raw {
+    double t, x[3], v[3], a[3], k[3];
+    float m;
+};
+
+template <bool PRED>
+__device__ __forceinline__ void load_raw(const EnsArgs &A, int64_t q, Raw &r) {
     const int64_t nt = A.nt;
-    double xi[EIT], yi[EIT], zi[EIT], ui[EIT], vi[EIT], wi[EIT];
-    int ip[EIT];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        r.x[c] = A.x[c * nt + q];
+        r.v[c] = A.v[c * nt + q];
+        if (PRED) {
+            r.a[c] = A.a[c * nt + q];
+            r.k[c] = A.k[c * nt + q];
+        }
+    }
+    if (PRED) r.t = A.t[q];
+    r.m = (float)A.m[q];
+}
+
+// Position and velocity predicted to tn (PRED) or as stored.
+template <bool PRED>
+__device__ __forceinline__ void raw_state(const Raw &r, double tn, double px[3], double pv[3]) {
+    if (PRED) {
+        predict_vals(tn - r.t, r.x, r.v, r.a, r.k, px, pv);
+    } else {
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            px[c] = r.x[c];
+            pv[c] = r.v[c];
+        }
+    }
+}
+
+// Minimum over the group (every thread gets it).
+__device__ __forceinline__ double group_min(double v, double *smin) {
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) v = fmin(v, __shfl_xor(v, o, 64));
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0) smin[threadIdx.x >> 6] = v;
+    __syncthreads();
+    double r = smin[0];
+#pragma unroll
+    for (int w = 1; w < EW; ++w) r = fmin(r, smin[w]);
+    return r;
+}
+
+// Pair sums of one work item of a cluster: block slots
+// [slot0, slot0 + NI * 64 / L) against the j range [j0, j1).  Lane l holds
+// slots slot0 + t * (64 / L) + l / L (t < NI) and takes every L-th j of its
+// wave's share of each tile, starting at l % L; the L partial sums of a
+// slot are added in float64 (butterfly, fixed order), then the waves' sums
+// in wave order.  With PRED every particle, i and j, is predicted to tn as
+// it is loaded; otherwise the stored state is used.  Only acceleration and
+// jerk are summed: the ensemble never reports the potential.  The self pair
+// adds exactly zero when eps2 is not tiny (r = w = 0 and m s^-3/2 finite), so
+// it is masked by index only for eps2 < 1e-12.  (Holding the next j tile
+// in registers while the current one is summed would cost the third group
+// per CU its registers; the co-resident groups hide the tile loads.)
+constexpr int EIT = 2;          // most i-slots per lane
+constexpr float EMASK = 1e-12f;  // below this eps2 the self pair is masked
+
+template <bool DS, bool PRED, int NI, int L>
+__device__ void ens_pair_item(const EnsArgs &A, int64_t base, float eps2, double tn,
+                              const Block &B, int n_i, int slot0, int j0, int j1, TileRec *tile,
+                              double (*red)[6 * EIT][64], double (&tot)[EIT][6]) {
+    constexpr int SPL = 64 / L;
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    const int wave = tid >> 6;
+    const int ph = lane % L;
+    double xi[NI], yi[NI], zi[NI], ui[NI], vi[NI], wi[NI];
+    int ip[NI];
     int lo = 0x7fffffff, hi = -1;
 #pragma unroll
-    for (int t = 0; t < EIT; ++t) {
-        const int slot = (int)(ib * 64 * EIT + t * 64 + lane);
-        const int sl = slot < n_i ? slot : n_i - 1;
-        ip[t] = act ? act[sl] : sl;  // cluster-local index
-        const int64_t q = base + ip[t];
-        xi[t] = src_x[q];
-        yi[t] = src_x[nt + q];
-        zi[t] = src_x[2 * nt + q];
-        ui[t] = src_v[q];
-        vi[t] = src_v[nt + q];
-        wi[t] = src_v[2 * nt + q];
+    for (int t = 0; t < NI; ++t) {
+        const int slot = slot0 + t * SPL + lane / L;
+        ip[t] = block_member(B, slot < n_i ? slot : n_i - 1);  // cluster-local index
+        Raw r;
+        load_raw<PRED>(A, base + ip[t], r);
+        double px[3], pv[3];
+        raw_state<PRED>(r, tn, px, pv);
+        xi[t] = px[0];
+        yi[t] = px[1];
+        zi[t] = px[2];
+        ui[t] = pv[0];
+        vi[t] = pv[1];
+        wi[t] = pv[2];
         lo = min(lo, ip[t]);
         hi = max(hi, ip[t]);
     }
+    const bool maskable = !(eps2 >= EMASK);
+    if (maskable) {
 #pragma unroll
-    for (int o = 32; o >= 1; o >>= 1) {
-        lo = min(lo, __shfl_xor(lo, o, 64));
-        hi = max(hi, __shfl_xor(hi, o, 64));
+        for (int o = 32; o >= 1; o >>= 1) {
+            lo = min(lo, __shfl_xor(lo, o, 64));
+            hi = max(hi, __shfl_xor(hi, o, 64));
+        }
     }
-    float sh[EIT][7], sl7[EIT][7];
+    float sh[NI][6], sl[NI][6];
 #pragma unroll
-    for (int t = 0; t < EIT; ++t)
+    for (int t = 0; t < NI; ++t)
 #pragma unroll
-        for (int c = 0; c < 7; ++c) sh[t][c] = sl7[t][c] = 0.0f;
+        for (int c = 0; c < 6; ++c) sh[t][c] = sl[t][c] = 0.0f;
     for (int jt = j0; jt < j1; jt += ETILE) {
         const int cnt = min(ETILE, j1 - jt);
         __syncthreads();
-        if ((int)threadIdx.x < cnt) {
-            const int64_t q = base + jt + threadIdx.x;
-            TileRec r;
-            r.x = src_x[q];
-            r.y = src_x[nt + q];
-            r.z = src_x[2 * nt + q];
-            r.u = src_v[q];
-            r.v = src_v[nt + q];
-            r.w = src_v[2 * nt + q];
-            r.m = (float)A.m[q];
-            tile[threadIdx.x] = r;
+        if (tid < cnt) {
+            Raw nxt;
+            load_raw<PRED>(A, base + jt + tid, nxt);
+            double px[3], pv[3];
+            raw_state<PRED>(nxt, tn, px, pv);
+            TileRec R;
+            R.x = px[0];
+            R.y = px[1];
+            R.z = px[2];
+            R.u = pv[0];
+            R.v = pv[1];
+            R.w = pv[2];
+            R.m = nxt.m;
+            tile[tid] = R;
         }
         __syncthreads();
         const int r0 = wave * 64, r1 = min(cnt, r0 + 64);
-        float in[EIT][7];
+        float in[NI][6];
 #pragma unroll
-        for (int t = 0; t < EIT; ++t)
+        for (int t = 0; t < NI; ++t)
 #pragma unroll
-            for (int c = 0; c < 7; ++c) in[t][c] = 0.0f;
+            for (int c = 0; c < 6; ++c) in[t][c] = 0.0f;
         auto body = [&](const TileRec &R, const int j, const bool mask)
             __attribute__((always_inline)) {
 #pragma unroll
-            for (int t = 0; t < EIT; ++t) {
+            for (int t = 0; t < NI; ++t) {
                 const float dx = (float)(R.x - xi[t]), dy = (float)(R.y - yi[t]);
                 const float dz = (float)(R.z - zi[t]);
                 const float du = (float)(R.u - ui[t]), dv = (float)(R.v - vi[t]);
@@ -234,8 +323,7 @@ __device__ void ens_pair_item(const EnsArgs &A, const double *src_x, const doubl
                 const float rv = fmaf(dz, dw, fmaf(dy, dv, dx * du));
                 const float rinv = __builtin_amdgcn_rsqf(s2);
                 const float rinv2 = rinv * rinv;
-                const float mr1 = mj * rinv;
-                const float mr3 = mr1 * rinv2;
+                const float mr3 = (mj * rinv) * rinv2;
                 const float w3 = (rv * rinv2) * -3.0f;
                 in[t][0] = fmaf(mr3, dx, in[t][0]);
                 in[t][1] = fmaf(mr3, dy, in[t][1]);
@@ -243,49 +331,61 @@ __device__ void ens_pair_item(const EnsArgs &A, const double *src_x, const doubl
                 in[t][3] = fmaf(mr3, fmaf(w3, dx, du), in[t][3]);
                 in[t][4] = fmaf(mr3, fmaf(w3, dy, dv), in[t][4]);
                 in[t][5] = fmaf(mr3, fmaf(w3, dz, dw), in[t][5]);
-                in[t][6] = fmaf(mj, rinv, in[t][6]);
             }
         };
-        if ((jt + r0 <= hi) && (jt + r1 > lo)) {
-            for (int r = r0; r < r1; ++r) body(tile[r], jt + r, true);
+        if (maskable && (jt + r0 <= hi) && (jt + r1 > lo)) {
+            for (int r = r0 + ph; r < r1; r += L) body(tile[r], jt + r, true);
         } else {
 #pragma unroll 4
-            for (int r = r0; r < r1; ++r) body(tile[r], jt + r, false);
+            for (int r = r0 + ph; r < r1; r += L) body(tile[r], jt + r, false);
         }
 #pragma unroll
-        for (int t = 0; t < EIT; ++t)
+        for (int t = 0; t < NI; ++t)
 #pragma unroll
-            for (int c = 0; c < 7; ++c) ds_fold(sh[t][c], sl7[t][c], in[t][c], DS);
+            for (int c = 0; c < 6; ++c) ds_fold(sh[t][c], sl[t][c], in[t][c], DS);
     }
 #pragma unroll
-    for (int t = 0; t < EIT; ++t) {
+    for (int t = 0; t < NI; ++t)
 #pragma unroll
-        for (int c = 0; c < 7; ++c) tot[t][c] = (double)sh[t][c] + (double)sl7[t][c];
-        tot[t][6] = -tot[t][6];
-    }
+        for (int c = 0; c < 6; ++c) {
+            double s = (double)sh[t][c] + (double)sl[t][c];
+#pragma unroll
+            for (int o = 1; o < L; o <<= 1) s += __shfl_xor(s, o, 64);
+            tot[t][c] = s;
+        }
     __syncthreads();
     if (wave > 0)
 #pragma unroll
-        for (int t = 0; t < EIT; ++t)
+        for (int t = 0; t < NI; ++t)
 #pragma unroll
-            for (int c = 0; c < 7; ++c) red[wave - 1][t * 7 + c][lane] = tot[t][c];
+            for (int c = 0; c < 6; ++c) red[wave - 1][t * 6 + c][lane] = tot[t][c];
     __syncthreads();
     if (wave == 0)
         for (int w = 1; w < EW; ++w)
 #pragma unroll
-            for (int t = 0; t < EIT; ++t)
+            for (int t = 0; t < NI; ++t)
 #pragma unroll
-                for (int c = 0; c < 7; ++c) tot[t][c] += red[w - 1][t * 7 + c][lane];
+                for (int c = 0; c < 6; ++c) tot[t][c] += red[w - 1][t * 6 + c][lane];
 }
 
-// Pair sums of a whole active block of a cluster, spread over the team:
-// results in anew/knew (component stride n_max); returns false on abort.
-template <bool DS>
-__device__ bool ens_pairs(const EnsArgs &A, const double *src_x, const double *src_v,
-                          int64_t base, int n, float eps2, const int32_t *act, int n_i, int g,
-                          int rank, int s_max, int n_max, double *anew, double *knew,
-                          double *part, uint32_t *bar, uint32_t &epoch, TileRec *tile,
-                          double (*red)[7 * EIT][64]) {
+// Width of the item of a block that starts at slot0: 128 slots (two per
+// lane) while more than 64 remain, else the narrowest of 64, 32, 16, 8
+// that holds the rest (the last three split j over 2, 4, 8 lanes).
+__device__ __forceinline__ int item_width(int rem, bool narrow) {
+    const int w = rem > 64 ? 128 : rem > 32 ? 64 : rem > 16 ? 32 : rem > 8 ? 16 : 8;
+    return narrow ? w : max(w, 64);
+}
+
+// Pair sums of a whole block (n_i slots) of a cluster of n particles,
+// spread over the team: results in anew/knew (slot-major, component stride
+// n_max); returns false on abort.  Items are 128 slots apart; the last one
+// is as narrow as its remainder allows.
+template <bool DS, bool PRED>
+__device__ bool ens_pairs(const EnsArgs &A, int64_t base, int n, float eps2, double tn,
+                          const Block &B, int n_i, int g, int rank, int s_max, int n_max,
+                          double *anew, double *knew, double *part, uint32_t *bar,
+                          uint32_t &epoch, TileRec *tile, double (*red)[6 * EIT][64]) {
+    if (n_i < 1) return team_barrier(bar, g, rank, epoch, A.abort, A.spin_limit);
     const int64_t nb = (n_i + 64 * EIT - 1) / (64 * EIT);
     int64_t S = (g + nb - 1) / nb;  // about one item per group
     int64_t smax = max(1, n / ETILE);
@@ -298,13 +398,30 @@ __device__ bool ens_pairs(const EnsArgs &A, const double *src_x, const double *s
     for (int64_t it = rank; it < items; it += g) {
         const int64_t ib = it % nb, sp = it / nb;
         const int j0 = (int)(sp * jchunk), j1 = min(n, j0 + jchunk);
-        double tot[EIT][7];
-        ens_pair_item<DS>(A, src_x, src_v, base, n, eps2, act, n_i, ib, j0, j1, tile, red, tot);
-        if ((threadIdx.x >> 6) == 0) {
+        const int slot0 = (int)(ib * 64 * EIT);
+        const int w = item_width(n_i - slot0, PRED);
+        double tot[EIT][6];
+        int ni = 1, L = 1;
+        if (w == 128) {
+            ens_pair_item<DS, PRED, 2, 1>(A, base, eps2, tn, B, n_i, slot0, j0, j1, tile, red, tot);
+            ni = 2;
+        } else if (w == 64) {
+            ens_pair_item<DS, PRED, 1, 1>(A, base, eps2, tn, B, n_i, slot0, j0, j1, tile, red, tot);
+        } else if (PRED && w == 32) {
+            ens_pair_item<DS, PRED, 1, 2>(A, base, eps2, tn, B, n_i, slot0, j0, j1, tile, red, tot);
+            L = 2;
+        } else if (PRED && w == 16) {
+            ens_pair_item<DS, PRED, 1, 4>(A, base, eps2, tn, B, n_i, slot0, j0, j1, tile, red, tot);
+            L = 4;
+        } else if (PRED) {
+            ens_pair_item<DS, PRED, 1, 8>(A, base, eps2, tn, B, n_i, slot0, j0, j1, tile, red, tot);
+            L = 8;
+        }
+        if ((threadIdx.x >> 6) == 0 && lane % L == 0) {
 #pragma unroll
             for (int t = 0; t < EIT; ++t) {
-                const int slot = (int)(ib * 64 * EIT + t * 64 + lane);
-                if (slot >= n_i) continue;
+                const int slot = slot0 + t * (64 / L) + lane / L;
+                if (t >= ni || slot >= n_i) continue;
                 if (S == 1) {
 #pragma unroll
                     for (int c = 0; c < 3; ++c) {
@@ -334,12 +451,33 @@ __device__ bool ens_pairs(const EnsArgs &A, const double *src_x, const double *s
     return team_barrier(bar, g, rank, epoch, A.abort, A.spin_limit);
 }
 
+__device__ __forceinline__ void store_relaxed(double *p, double v) {
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ double load_relaxed(const double *p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// One block step of a cluster is three team phases, each closed by a team
+// barrier:
+//   A  every group scans its slice once: it compacts the members of the
+//      block (t_i + dt_i == t_next) and takes the minimum of t_i + dt_i over
+//      the others, which do not move in this step;
+//   B  pair sums of the block, every particle predicted to t_next as it is
+//      loaded (no predicted copy of the state is stored);
+//   C  every group corrects the members of its own slice (predicting them
+//      again, bitwise the same) and takes the minimum of their new t + dt.
+// The next t_next is the minimum over the groups of both minima, so the
+// block time needs no pass of its own.  The per-group minima are
+// double-buffered by step parity: a group may publish the next step's
+// values while a slower one still reads this step's.
 template <bool DS>
-__global__ __launch_bounds__(ETH) void ensemble_kernel(const EnsArgs A) {
+__global__ __launch_bounds__(ETH, 3) void ensemble_kernel(const EnsArgs A) {
     __shared__ TileRec tile[ETILE];
-    __shared__ double red[EW - 1][7 * EIT][64];
-    __shared__ double smin[ETH];
-    __shared__ int scount[ETH];
+    __shared__ double red[EW - 1][6 * EIT][64];
+    __shared__ double smin[EW];
+    __shared__ int scount[4 * EW];
+    __shared__ int spre[65];
     const int team = A.wg_team[blockIdx.x];
     const int rank = A.wg_rank[blockIdx.x];
     const EnsTeam T = A.teams[team];
@@ -348,16 +486,18 @@ __global__ __launch_bounds__(ETH) void ensemble_kernel(const EnsArgs A) {
     uint32_t epoch = 0;
     double *scr = A.scratch + T.scratch_off;
     const int n_max = T.n_max;
-    // scratch layout (doubles): pmin[g] | pcnt[g] | active[n_max] (int32) |
-    // anew[3 n_max] | knew[3 n_max] | part[s_max * 6 * n_max]
-    double *pmin = scr;
-    int64_t *pcnt = (int64_t *)(scr + g);
-    int32_t *act = (int32_t *)(scr + 2 * g);
-    double *anew = scr + 2 * g + (n_max + 1) / 2;
+    // scratch layout (doubles): pm[2 parities][2 kinds][g] | pcnt[g] (int32)
+    // | act[n_max] (int32) | anew[3 n_max] | knew[3 n_max] |
+    // part[s_max * 6 * n_max]
+    double *pm = scr;
+    int32_t *pcnt = (int32_t *)(scr + 4 * g);
+    int32_t *act = (int32_t *)(scr + 5 * g);
+    double *anew = scr + 5 * g + (n_max + 1) / 2;
     double *knew = anew + 3 * (int64_t)n_max;
     double *part = knew + 3 * (int64_t)n_max;
     const int64_t nt = A.nt;
     const int tid = threadIdx.x;
+    const int lane = tid & 63, wave = tid >> 6;
 
     for (int ci = T.cl_begin; ci < T.cl_end; ++ci) {
         const int c = A.cl_order[ci];
@@ -370,9 +510,11 @@ __global__ __launch_bounds__(ETH) void ensemble_kernel(const EnsArgs A) {
         if (rank == 0 && tid == 0) A.clock[2 * c] = wall_clock64();
 
         // ---- initialisation: pair sums of every particle, initial steps
-        if (!ens_pairs<DS>(A, A.x, A.v, base, n, eps2, nullptr, n, g, rank, T.s_max, n_max, anew,
-                           knew, part, bar, epoch, tile, red))
+        const Block whole{nullptr, spre, g, per, n};
+        if (!ens_pairs<DS, false>(A, base, n, eps2, 0.0, whole, n, g, rank, T.s_max, n_max,
+                                  anew, knew, part, bar, epoch, tile, red))
             return;
+        double mn = INFINITY;
         for (int i = p0 + tid; i < p1; i += ETH) {
             const int64_t q = base + i;
 #pragma unroll
@@ -382,104 +524,120 @@ __global__ __launch_bounds__(ETH) void ensemble_kernel(const EnsArgs A) {
             }
             int32_t st = 0;
             A.t[q] = 0.0;
-            A.dt[q] = initial_dt_one(q, nt, 0.0, A.a, A.k, A.eta_s, A.dt_max, A.dt_min, &st);
+            const double d = initial_dt_one(q, nt, 0.0, A.a, A.k, A.eta_s, A.dt_max, A.dt_min,
+                                            &st);
+            A.dt[q] = d;
+            mn = fmin(mn, 0.0 + d);
             if (st) atomicOr(A.status, st);
+        }
+        mn = group_min(mn, smin);
+        if (tid == 0) {
+            store_relaxed(&pm[rank], INFINITY);
+            store_relaxed(&pm[g + rank], mn);
         }
         if (!team_barrier(bar, g, rank, epoch, A.abort, A.spin_limit)) return;
 
         int64_t my_steps = 0, my_inter = 0;
+        int par = 0;
         for (;;) {
-            // ---- t_next = min(t + dt) over the cluster
-            double mn = INFINITY;
-            for (int i = p0 + tid; i < p1; i += ETH) mn = fmin(mn, A.t[base + i] + A.dt[base + i]);
-            smin[tid] = mn;
-            __syncthreads();
-            for (int o = ETH / 2; o > 0; o >>= 1) {
-                if (tid < o) smin[tid] = fmin(smin[tid], smin[tid + o]);
-                __syncthreads();
-            }
-            if (tid == 0) pmin[rank] = smin[0];
-            if (!team_barrier(bar, g, rank, epoch, A.abort, A.spin_limit)) return;
             double tn = INFINITY;
             for (int r = 0; r < g; ++r)
-                tn = fmin(tn, __hip_atomic_load(&pmin[r], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+                tn = fmin(tn, fmin(load_relaxed(&pm[(2 * par) * g + r]),
+                                   load_relaxed(&pm[(2 * par + 1) * g + r])));
             if (!(tn <= A.t_end)) break;
+            const int nx = par ^ 1;
 
-            // ---- active block, ascending: count per group, then place
-            int cnt = 0;
-            for (int i = p0 + tid; i < p1; i += ETH) cnt += (A.t[base + i] + A.dt[base + i] == tn);
-            scount[tid] = cnt;
-            __syncthreads();
-            for (int o = ETH / 2; o > 0; o >>= 1) {
-                if (tid < o) scount[tid] += scount[tid + o];
+            // ---- A: the block's members in the slice, ascending, and the
+            // minimum of t + dt over the rest of the slice
+            int local = 0;
+            double rmin = INFINITY;
+            const unsigned long long below = (1ull << lane) - 1ull;
+            for (int pb = p0; pb < p1; pb += 4 * ETH) {
+                bool f[4];
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    const int i = pb + u * ETH + tid;
+                    f[u] = false;
+                    if (i < p1) {
+                        const double s = A.t[base + i] + A.dt[base + i];
+                        f[u] = (s == tn);
+                        if (!f[u]) rmin = fmin(rmin, s);
+                    }
+                }
+                unsigned long long bal[4];
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    bal[u] = __ballot(f[u]);
+                    if (lane == 0) scount[u * EW + wave] = __popcll(bal[u]);
+                }
+                __syncthreads();
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    int woff = 0, tot = 0;
+#pragma unroll
+                    for (int w = 0; w < EW; ++w) {
+                        const int cw = scount[u * EW + w];
+                        woff += (w < wave) ? cw : 0;
+                        tot += cw;
+                    }
+                    if (f[u]) act[p0 + local + woff + __popcll(bal[u] & below)] = pb + u * ETH + tid;
+                    local += tot;
+                }
                 __syncthreads();
             }
-            if (tid == 0) pcnt[rank] = scount[0];
-            if (!team_barrier(bar, g, rank, epoch, A.abort, A.spin_limit)) return;
-            int64_t before = 0, n_i = 0;
-            for (int r = 0; r < g; ++r) {
-                const int64_t cr = __hip_atomic_load(&pcnt[r], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                if (r < rank) before += cr;
-                n_i += cr;
+            rmin = group_min(rmin, smin);
+            if (tid == 0) {
+                store_relaxed(&pm[(2 * nx) * g + rank], rmin);
+                __hip_atomic_store(&pcnt[rank], local, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             }
-            {
-                // place the active indices (ascending) and predict every
-                // particle of the slice to tn in the same pass
-                const int lane = tid & 63, wave = tid >> 6;
-                int64_t off = before;
-                for (int pbase = p0; pbase < p1; pbase += ETH) {
-                    const int i = pbase + tid;
-                    bool f = false;
-                    if (i < p1) {
-                        const int64_t q = base + i;
-                        const double tq = A.t[q];
-                        f = (tq + A.dt[q] == tn);
-                        double px[3], pv[3];
-                        predict_one(tn - tq, A.x, A.v, A.a, A.k, q, nt, px, pv);
+            if (!team_barrier(bar, g, rank, epoch, A.abort, A.spin_limit)) return;
+            if (tid < 64) {
+                int cs = tid < g ? __hip_atomic_load(&pcnt[tid], __ATOMIC_RELAXED,
+                                                     __HIP_MEMORY_SCOPE_AGENT)
+                                 : 0;
 #pragma unroll
-                        for (int cc = 0; cc < 3; ++cc) {
-                            A.xp[cc * nt + q] = px[cc];
-                            A.vp[cc * nt + q] = pv[cc];
-                        }
-                    }
-                    const unsigned long long bal = __ballot(f);
-                    const int bef = __popcll(bal & ((1ull << lane) - 1ull));
-                    __syncthreads();
-                    if (lane == 0) scount[wave] = __popcll(bal);
-                    __syncthreads();
-                    int woff = 0, tot = 0;
-                    for (int w = 0; w < EW; ++w) {
-                        if (w < wave) woff += scount[w];
-                        tot += scount[w];
-                    }
-                    if (f) act[off + woff + bef] = i;
-                    off += tot;
+                for (int o = 1; o < 64; o <<= 1) {
+                    const int y = __shfl_up(cs, o, 64);
+                    cs += (lane >= o) ? y : 0;
                 }
+                spre[tid + 1] = cs;
+                if (tid == 0) spre[0] = 0;
             }
-            if (!team_barrier(bar, g, rank, epoch, A.abort, A.spin_limit)) return;
+            __syncthreads();
+            const int n_i = spre[g];
+            const Block blk{act, spre, g, per, n};
 
-            // ---- pair sums of the block at the predicted state
-            if (!ens_pairs<DS>(A, A.xp, A.vp, base, n, eps2, act, (int)n_i, g, rank, T.s_max, n_max,
-                               anew, knew, part, bar, epoch, tile, red))
+            // ---- B: pair sums of the block at the predicted state
+            if (!ens_pairs<DS, true>(A, base, n, eps2, tn, blk, n_i, g, rank, T.s_max, n_max,
+                                     anew, knew, part, bar, epoch, tile, red))
                 return;
 
-            // ---- correct the block
-            const int per_i = (int)((n_i + g - 1) / g);
-            const int s0 = min((int)n_i, rank * per_i), s1 = min((int)n_i, s0 + per_i);
-            for (int s = s0 + tid; s < s1; s += ETH) {
-                const int64_t q = base + act[s];
+            // ---- C: correct the slice's members; minimum of the new t + dt
+            const int s_own = spre[rank];
+            double nmin = INFINITY;
+            for (int kk = tid; kk < local; kk += ETH) {
+                const int s = s_own + kk;
+                const int64_t q = base + act[p0 + kk];
+                Raw r;
+                load_raw<true>(A, q, r);
+                double px[3], pv[3];
+                raw_state<true>(r, tn, px, pv);
                 double a1v[3], k1v[3];
 #pragma unroll
                 for (int cc = 0; cc < 3; ++cc) {
                     a1v[cc] = anew[cc * n_max + s];
                     k1v[cc] = knew[cc * n_max + s];
                 }
-                const int32_t st = correct_one(q, nt, A.xp, A.vp, a1v, k1v, A.eta, A.dt_max,
-                                               A.dt_min, 0, A.t, A.dt, A.x, A.v, A.a, A.k);
+                const int32_t st = correct_vals(q, nt, px, pv, a1v, k1v, A.eta, A.dt_max,
+                                                A.dt_min, 0, A.t, A.dt, A.x, A.v, A.a, A.k);
                 if (st) atomicOr(A.status, st);
+                nmin = fmin(nmin, A.t[q] + A.dt[q]);
             }
+            nmin = group_min(nmin, smin);
+            if (tid == 0) store_relaxed(&pm[(2 * nx + 1) * g + rank], nmin);
             my_steps += 1;
-            my_inter += n_i * n;
+            my_inter += (int64_t)n_i * n;
+            par = nx;
             if (!team_barrier(bar, g, rank, epoch, A.abort, A.spin_limit)) return;
         }
         if (rank == 0 && tid == 0) {
@@ -487,8 +645,8 @@ __global__ __launch_bounds__(ETH) void ensemble_kernel(const EnsArgs A) {
             A.inter[c] = my_inter;
             A.clock[2 * c + 1] = wall_clock64();
         }
-        // the next cluster's initialisation writes anew/knew and act: make
-        // sure every group of the team is past this cluster
+        // the next cluster's initialisation rewrites the scratch: make sure
+        // every group of the team is past this cluster
         if (!team_barrier(bar, g, rank, epoch, A.abort, A.spin_limit)) return;
     }
 }
@@ -589,7 +747,7 @@ static Plan plan_teams(const std::vector<int64_t> &sizes, int G, int max_team,
         T.n_max = nmax;
         T.s_max = std::min(EMAXSPLIT, std::max(1, T.size));
         T.scratch_off = P.scratch;
-        P.scratch += 2 * T.size + (nmax + 1) / 2 + 6 * (int64_t)nmax +
+        P.scratch += 5 * T.size + (nmax + 1) / 2 + 6 * (int64_t)nmax +
                      (int64_t)T.s_max * 6 * nmax + 8;
         const int team_id = (int)P.teams.size();
         P.teams.push_back(T);
@@ -648,15 +806,14 @@ extern "C" int nbody_ensemble_run(nbody_ctx *ctx, const nbody_ensemble *e, doubl
     std::vector<EnsCluster> hc(nc);
     for (int c = 0; c < nc; ++c) hc[c] = EnsCluster{e->offsets[c], (int32_t)sizes[c], (float)e->eps2[c]};
 
-    // one device block: tables, counters, scratch, predicted state
+    // one device block: tables, counters, team scratch
     auto al = [](size_t b) { return (b + 255) & ~size_t(255); };
     const size_t b_cl = al(sizeof(EnsCluster) * nc), b_ord = al(4 * P.order.size()),
                  b_tm = al(sizeof(EnsTeam) * nteams), b_wg = al(4 * (size_t)grid),
                  b_bar = al(4 * 64 * (size_t)nteams), b_cnt = al(8 * (size_t)nc),
                  b_clk = al(16 * (size_t)nc),
-                 b_fl = al(8), b_scr = al(8 * (size_t)P.scratch), b_st = al(8 * 3 * (size_t)nt);
-    const size_t total =
-        b_cl + b_ord + b_tm + 2 * b_wg + b_bar + 2 * b_cnt + b_clk + b_fl + b_scr + 2 * b_st;
+                 b_fl = al(8), b_scr = al(8 * (size_t)P.scratch);
+    const size_t total = b_cl + b_ord + b_tm + 2 * b_wg + b_bar + 2 * b_cnt + b_clk + b_fl + b_scr;
     NB_TRY(ensure(ctx, &ctx->ens, &ctx->ens_bytes, total));
     char *p = (char *)ctx->ens;
     EnsCluster *d_cl = (EnsCluster *)p; p += b_cl;
@@ -669,9 +826,7 @@ extern "C" int nbody_ensemble_run(nbody_ctx *ctx, const nbody_ensemble *e, doubl
     int64_t *d_inter = (int64_t *)p; p += b_cnt;
     uint64_t *d_clock = (uint64_t *)p; p += b_clk;
     int32_t *d_flags = (int32_t *)p; p += b_fl;
-    double *d_scr = (double *)p; p += b_scr;
-    double *d_xp = (double *)p; p += b_st;
-    double *d_vp = (double *)p;
+    double *d_scr = (double *)p;
 
     NB_TRY(hip_check(ctx, hipMemcpyAsync(d_cl, hc.data(), sizeof(EnsCluster) * nc, hipMemcpyHostToDevice, ctx->stream), "copy"));
     NB_TRY(hip_check(ctx, hipMemcpyAsync(d_ord, P.order.data(), 4 * P.order.size(), hipMemcpyHostToDevice, ctx->stream), "copy"));
@@ -692,7 +847,6 @@ extern "C" int nbody_ensemble_run(nbody_ctx *ctx, const nbody_ensemble *e, doubl
     EnsArgs A;
     A.nt = nt;
     A.t = e->t; A.dt = e->dt; A.x = e->x; A.v = e->v; A.a = e->a; A.k = e->k; A.m = e->m;
-    A.xp = d_xp; A.vp = d_vp;
     A.eta = e->eta; A.eta_s = e->eta_s; A.dt_max = e->dt_max; A.dt_min = e->dt_min;
     A.t_end = t_end;
     A.cl = d_cl; A.cl_order = d_ord; A.teams = d_tm; A.wg_team = d_wgt; A.wg_rank = d_wgr;

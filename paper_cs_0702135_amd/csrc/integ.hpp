@@ -7,27 +7,43 @@
 
 namespace nb {
 
+// Predictor from values: h = t_target - t_i.
+__device__ __forceinline__ void predict_vals(double h, const double x[3], const double v[3],
+                                             const double a[3], const double k[3], double px[3],
+                                             double pv[3]) {
+#pragma clang fp contract(off)
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        px[c] = x[c] + (v[c] + (h / 2.0) * (a[c] + (h / 3.0) * k[c])) * h;
+        pv[c] = v[c] + (a[c] + (h / 2.0) * k[c]) * h;
+    }
+}
+
 // Predictor: h = t_target - t_i; q points at component 0, stride cs.
 __device__ __forceinline__ void predict_one(double h, const double *x, const double *v,
                                             const double *a, const double *k, int64_t q,
                                             int64_t cs, double px[3], double pv[3]) {
-#pragma clang fp contract(off)
+    double xs[3], vs[3], as[3], ks[3];
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
         const int64_t e = q + c * cs;
-        px[c] = x[e] + (v[e] + (h / 2.0) * (a[e] + (h / 3.0) * k[e])) * h;
-        pv[c] = v[e] + (a[e] + (h / 2.0) * k[e]) * h;
+        xs[c] = x[e];
+        vs[c] = v[e];
+        as[c] = a[e];
+        ks[c] = k[e];
     }
+    predict_vals(h, xs, vs, as, ks, px, pv);
 }
 
-// Corrector and new step of one particle.  a1, k1: the new force and jerk.
-// State arrays at element q (component stride cs); returns status bits.
-__device__ __forceinline__ int32_t correct_one(int64_t q, int64_t cs, const double *xp,
-                                               const double *vp, const double a1v[3],
-                                               const double k1v[3], double eta, double dt_max,
-                                               double dt_min, int fixed_dt, double *t,
-                                               double *dtv, double *x, double *v, double *a,
-                                               double *k) {
+// Corrector and new step of one particle.  xp, vp: its predicted position
+// and velocity; a1, k1: the new force and jerk.  State arrays at element q
+// (component stride cs); returns status bits.
+__device__ __forceinline__ int32_t correct_vals(int64_t q, int64_t cs, const double xp[3],
+                                                const double vp[3], const double a1v[3],
+                                                const double k1v[3], double eta, double dt_max,
+                                                double dt_min, int fixed_dt, double *t,
+                                                double *dtv, double *x, double *v, double *a,
+                                                double *k) {
 #pragma clang fp contract(off)
     int32_t st = 0;
     const double h = dtv[q];
@@ -40,8 +56,8 @@ __device__ __forceinline__ int32_t correct_one(int64_t q, int64_t cs, const doub
         const double a1 = a1v[c], k1 = k1v[c];
         const double A3 = 2.0 * (a0 - a1) + (k0 + k1) * h;
         const double A2 = -3.0 * (a0 - a1) - (2.0 * k0 + k1) * h;
-        x[e] = xp[e] + (A2 / 12.0 + A3 / 20.0) * h * h;
-        v[e] = vp[e] + (A2 / 3.0 + A3 / 4.0) * h;
+        x[e] = xp[c] + (A2 / 12.0 + A3 / 20.0) * h * h;
+        v[e] = vp[c] + (A2 / 3.0 + A3 / 4.0) * h;
         a[e] = a1;
         k[e] = k1;
         a2v[c] = (2.0 * A2 + 6.0 * A3) / (h * h);
@@ -73,6 +89,23 @@ __device__ __forceinline__ int32_t correct_one(int64_t q, int64_t cs, const doub
         dtv[q] = d;
     }
     return st;
+}
+
+// Corrector reading the predicted state from arrays (element q, stride cs).
+__device__ __forceinline__ int32_t correct_one(int64_t q, int64_t cs, const double *xp,
+                                               const double *vp, const double a1v[3],
+                                               const double k1v[3], double eta, double dt_max,
+                                               double dt_min, int fixed_dt, double *t,
+                                               double *dtv, double *x, double *v, double *a,
+                                               double *k) {
+    double px[3], pv[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        px[c] = xp[q + c * cs];
+        pv[c] = vp[q + c * cs];
+    }
+    return correct_vals(q, cs, px, pv, a1v, k1v, eta, dt_max, dt_min, fixed_dt, t, dtv, x, v, a,
+                        k);
 }
 
 // Initial step of one particle (a, k at element q, stride cs).
