@@ -68,6 +68,8 @@ def main():
                     help="target duration of the oracle's CPU-baseline sample")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-aux", action="store_true")
+    ap.add_argument("--no-ablation", action="store_true",
+                    help="skip the per-cluster driver ablation of the ensemble (many launches)")
     ap.add_argument("--retune", action="store_true")
     ap.add_argument("--calib-copy", action="store_true",
                     help="only run one plain device copy of 1 GiB (HBM-counter calibration)")
@@ -264,19 +266,20 @@ def main():
         aux["ensemble256_grid_teams"] = [grid, teams]
         # ablation: the same clusters integrated one after the other, each
         # with the single-system block-step driver (several launches per step)
-        ta = time.perf_counter()
-        abl_inter = 0
-        for c in range(len(sizes)):
-            lo_, hi_ = int(off[c]), int(off[c + 1])
-            sc = nb.System(EP[:, lo_:hi_].contiguous(), EV[:, lo_:hi_].contiguous(),
-                           EM[lo_:hi_].contiguous(), float(eps_c[c]) ** 2,
-                           eta=ce.eta, dt_max=ce.dt_max, mode=args.mode)
-            sc.run(ce.t_end)
-            abl_inter += sc.interactions
-        torch.cuda.synchronize()
-        tb = time.perf_counter()
-        aux["ensemble256_per_cluster_driver_seconds"] = tb - ta
-        aux["ensemble256_per_cluster_driver_interactions_per_s"] = abl_inter / (tb - ta)
+        if not args.no_ablation:
+            ta = time.perf_counter()
+            abl_inter = 0
+            for c in range(len(sizes)):
+                lo_, hi_ = int(off[c]), int(off[c + 1])
+                sc = nb.System(EP[:, lo_:hi_].contiguous(), EV[:, lo_:hi_].contiguous(),
+                               EM[lo_:hi_].contiguous(), float(eps_c[c]) ** 2,
+                               eta=ce.eta, dt_max=ce.dt_max, mode=args.mode)
+                sc.run(ce.t_end)
+                abl_inter += sc.interactions
+            torch.cuda.synchronize()
+            tb = time.perf_counter()
+            aux["ensemble256_per_cluster_driver_seconds"] = tb - ta
+            aux["ensemble256_per_cluster_driver_interactions_per_s"] = abl_inter / (tb - ta)
 
         # differentiable run: N = 16384, eps = 1/512, 64 shared steps of 1/512,
         # checkpoints every 8 steps; forward + backward through the HIP adjoint

@@ -78,7 +78,8 @@ __global__ __launch_bounds__(64 * W) void force_adjoint_kernel(const KArgs a,
 
     __shared__ double red[W > 1 ? W - 1 : 1][7][64];
 
-    for (int64_t item = blockIdx.x; item < items; item += gridDim.x) {
+    for (int64_t q = blockIdx.x; q < items; q += gridDim.x) {
+        const int64_t item = xcd_item(q, items);
         const int64_t ib = item % nb;
         const int64_t sp = item / nb;
         const int j0 = (int)(sp * jchunk);

@@ -48,6 +48,20 @@ __host__ __device__ inline int64_t choose_splits(int64_t n_i, int64_t n_j, int i
     return s;
 }
 
+// Workgroups are dispatched round-robin over the 8 XCDs of the chip, each
+// with its own L2.  Items are numbered split-major (item = split * nb +
+// i-block), so mapping workgroup q to item (q % 8) * (items / 8) + q / 8
+// hands each XCD a contiguous run of items, i.e. one or two j chunks that
+// its L2 serves to all of its groups, instead of every XCD streaming every
+// chunk.  The map is a bijection on [0, items) (the remainder beyond a
+// multiple of 8 maps to itself), so results never depend on the dispatch.
+constexpr int kXcds = 8;
+
+__device__ __forceinline__ int64_t xcd_item(int64_t q, int64_t items) {
+    const int64_t per = items / kXcds;
+    return q < per * kXcds ? (q % kXcds) * per + q / kXcds : q;
+}
+
 __device__ __forceinline__ void two_sum_acc(float &hi, float &lo, float x) {
     const float s = hi + x;
     const float bp = s - hi;
