@@ -57,6 +57,101 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+def fit_power_law(x, y):
+    """Least-squares fit of y = c x^p in log-log space; returns (c, p)."""
+    import numpy as np
+    p, lc = np.polyfit(np.log(np.asarray(x, dtype=float)), np.log(np.asarray(y, dtype=float)), 1)
+    return float(np.exp(lc)), float(p)
+
+
+def paper_table(args):
+    """The Section 4 results-table protocol on one GPU: for each N, one
+    seeded Plummer realisation, eps = 1/256, eta = 0.02, dt_max = 1/8,
+    block steps from t = 0 to 1/4 (untimed), then timed from 1/4 to 1/2.
+    Prints one JSON line with a row per N (seconds, block steps, mean block
+    size, interactions/s, energy drift) next to the paper's printed seconds
+    for its GeForce 8800GTX and GRAPE-6Af (other hardware: context only),
+    and power-law fits of the block statistics next to the paper's."""
+    import numpy as np
+    import torch
+
+    import paper_cs_0702135_amd as nb
+    from workloads.plummer import CONFIGS, plummer, table_protocol_seed
+
+    cfg = CONFIGS["table_protocol"]
+    t_from = cfg.extra["timed_from"]
+    with open(os.path.join(ROOT, "tests", "golden", "paper_fits.json")) as f:
+        gold = json.load(f)
+    paper = gold["results_table_seconds"]
+    nb.tune_clear()
+    rows = []
+    for n in cfg.extra["n_list"]:
+        if n > args.table_max_n:
+            break
+        pos, vel, m = plummer(n, table_protocol_seed(n))
+        P, V, M = (torch.from_numpy(a).cuda() for a in (pos, vel, m))
+        s = nb.System(P, V, M, cfg.eps2, eta=cfg.eta, eta_s=cfg.eta_s, dt_max=cfg.dt_max,
+                      mode=args.mode)
+        e0 = s.energy()
+        # the untimed first part carries the pair-kernel event timing
+        nb.profile(1)
+        steps0 = s.run(t_from)
+        torch.cuda.synchronize()
+        force_ms, reduce_ms, launches = nb.profile(0)
+        inter0 = s.interactions
+        ta = time.perf_counter()
+        steps1 = s.run(cfg.t_end)
+        torch.cuda.synchronize()
+        tb = time.perf_counter()
+        inter1 = s.interactions - inter0
+        e1 = s.energy()
+        k = paper["n"].index(n)
+        row = {
+            "n": n,
+            "seconds": tb - ta,
+            "block_steps": steps1,
+            "block_steps_0_to_quarter": steps0,
+            "mean_block": inter1 / max(1, steps1) / n,
+            "interactions_per_s": inter1 / (tb - ta),
+            "ms_per_block_step": (tb - ta) / max(1, steps1) * 1e3,
+            "energy_drift_per_time_unit": abs((e1 - e0) / e0) / cfg.t_end,
+            "pair_kernel_tflops_0_to_quarter": FLOPS_PER_INTERACTION * inter0 / (force_ms * 1e-3) / 1e12,
+            "pair_kernel_frac_0_to_quarter": FLOPS_PER_INTERACTION * inter0 / (force_ms * 1e-3) / 1e12
+            / FP32_PEAK_TFLOPS,
+            "pair_kernel_launches_0_to_quarter": launches,
+            "paper_8800gtx_seconds": paper["geforce8800gtx"][k],
+            "paper_grape6af_seconds": paper["grape6af"][k],
+        }
+        rows.append(row)
+        log("table: N=%d %.4f s, %d block steps (mean block %.1f), drift/unit %.2e"
+            % (n, row["seconds"], steps1, row["mean_block"], row["energy_drift_per_time_unit"]))
+        del s, P, V, M
+    ns = [r["n"] for r in rows]
+    fits = {}
+    if len(rows) >= 2:
+        window = cfg.t_end - t_from
+        fits["mean_block"] = fit_power_law(ns, [r["mean_block"] for r in rows])
+        fits["block_steps_per_time_unit"] = fit_power_law(
+            ns, [r["block_steps"] / window for r in rows])
+        fits["paper_mean_block"] = (gold["n_block"]["coef"], gold["n_block"]["exp"])
+        fits["paper_block_steps_per_time_unit"] = (gold["n_steps_per_time_unit"]["coef"],
+                                                   gold["n_steps_per_time_unit"]["exp"])
+    out = {
+        "metric": "wall-clock seconds of t = 1/4 -> 1/2 (Section 4 results-table protocol)",
+        "unit": "s",
+        "higher_is_better": False,
+        "n_gpus": 1,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "plummer N=256..524288 (one seeded realisation per N), "
+                               "eps=1/256, eta=0.02, dt_max=1/8, block steps t: 0 -> 1/2, "
+                               "timed over 1/4 -> 1/2", "accumulation": args.mode},
+        "rows": rows,
+        "fits": fits,
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -71,6 +166,10 @@ def main():
     ap.add_argument("--no-ablation", action="store_true",
                     help="skip the per-cluster driver ablation of the ensemble (many launches)")
     ap.add_argument("--retune", action="store_true")
+    ap.add_argument("--paper-table", action="store_true",
+                    help="run the Section 4 results-table protocol instead of the default step")
+    ap.add_argument("--table-max-n", type=int, default=1 << 19,
+                    help="largest N of the results-table protocol")
     ap.add_argument("--calib-copy", action="store_true",
                     help="only run one plain device copy of 1 GiB (HBM-counter calibration)")
     args = ap.parse_args()
@@ -90,6 +189,10 @@ def main():
               "(the j-parallel sharding is a design note only); run with --gpus 1.",
               file=sys.stderr)
         sys.exit(2)
+
+    if args.paper_table:
+        paper_table(args)
+        return
 
     import numpy as np
     import torch
@@ -313,6 +416,41 @@ def main():
         torch.cuda.synchronize()
         aux["grad16k_adjoint_pairs_per_s"] = 5 * cg.n * (cg.n - 1.0) / (
             e0.elapsed_time(e1) * 1e-3)
+        del GP, GV, GM, P0, xf, tgt, xT
+
+        # beyond 2^20: N = 9e6 pair sums of seeded active subsets (both
+        # accumulations); N = 2^22 initialisation and a few block steps
+        c9 = CONFIGS["plummer9m"]
+        p9 = [torch.from_numpy(a).cuda() for a in plummer(c9.n, c9.seed)]
+        big = {}
+        for n_i in c9.extra["n_i"]:
+            idx = torch.from_numpy(random_active_set(c9.n, n_i, c9.seed + n_i)).cuda()
+            for md in ("fp32", "ds"):
+                nb.force(*p9, c9.eps2, idx, md)
+                torch.cuda.synchronize()
+                e0.record()
+                nb.force(*p9, c9.eps2, idx, md)
+                e1.record()
+                torch.cuda.synchronize()
+                big["%s_n_i_%d" % (md, n_i)] = n_i * (c9.n - 1.0) / (e0.elapsed_time(e1) * 1e-3)
+        aux["plummer9m_force_interactions_per_s"] = big
+        del p9
+        c4 = CONFIGS["plummer4m"]
+        p4 = [torch.from_numpy(a).cuda() for a in plummer(c4.n, c4.seed)]
+        torch.cuda.synchronize()
+        ta = time.perf_counter()
+        s4 = nb.System(*p4, c4.eps2, eta=c4.eta, dt_max=c4.dt_max, mode=args.mode)
+        torch.cuda.synchronize()
+        tb = time.perf_counter()
+        steps4 = s4.step(8)
+        torch.cuda.synchronize()
+        tc = time.perf_counter()
+        aux["plummer4m_init_seconds"] = tb - ta
+        aux["plummer4m_block_steps"] = steps4
+        aux["plummer4m_ms_per_block_step"] = (tc - tb) / max(1, steps4) * 1e3
+        aux["plummer4m_mean_block"] = s4.interactions / max(1, steps4) / c4.n
+        aux["plummer4m_block_step_interactions_per_s"] = s4.interactions / (tc - tb)
+        del s4, p4
         out["aux"] = aux
 
     if not args.no_cpu:

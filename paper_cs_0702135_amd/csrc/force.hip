@@ -20,6 +20,7 @@
 //     in split order by a second kernel.
 // The self pair is skipped by index: tiles whose j range can contain one of
 // the wave's own indices take a masked path.
+#include <algorithm>
 #include <cmath>
 
 #include "common.hpp"
@@ -429,14 +430,21 @@ static force_fn pick_kernel(const ForceShape &s, bool ds) {
 }
 
 
-static ForceShape default_shape(const nbody_ctx *ctx) {
+// Built-in shape for an active block of about n_i particles, following what
+// the autotuner finds on the MI355X: blocks below 256 keep one i per lane
+// and four waves splitting j; larger blocks take two i per lane (two
+// independent chains per lane hide the rsq and FMA latencies) and two
+// waves.  The target of 128 groups per CU (32768 in all) makes the j splits
+// small enough for the groups resident on an XCD to share their j chunk
+// in L2.
+static ForceShape default_shape(const nbody_ctx *ctx, int64_t n_i) {
     ForceShape s;
     s.rep = REP_F64;
-    s.it = 1;
-    s.waves = 4;
+    s.it = n_i >= 256 ? 2 : 1;
+    s.waves = n_i >= 1024 ? 2 : 4;
     s.tile = 128;
     s.min_j_wave = 64;
-    s.target_groups = 8 * ctx->cus;
+    s.target_groups = 128 * ctx->cus;
     return s;
 }
 
@@ -444,14 +452,16 @@ ForceShape pick_shape(const nbody_ctx *ctx, int64_t n_i, int64_t n_j) {
     (void)n_j;
     for (const TuneEntry &e : ctx->tune)
         if (e.n_i_lo >= 0 && n_i >= e.n_i_lo && n_i < e.n_i_hi) return e.shape;
-    return default_shape(ctx);
+    return default_shape(ctx, n_i);
 }
 
+// Shape of the block-step launches, whose n_i is only known on the device:
+// the tuned entry for them, else the built-in shape for a typical block of
+// a system of n particles (about 0.1 n^0.9 at eta = 0.02).
 ForceShape dynamic_shape(const nbody_ctx *ctx, int64_t n) {
-    (void)n;
     for (const TuneEntry &e : ctx->tune)
         if (e.n_i_lo < 0) return e.shape;
-    return default_shape(ctx);
+    return default_shape(ctx, (int64_t)(0.1 * std::pow((double)n, 0.9)));
 }
 
 int launch_force(nbody_ctx *ctx, const ForceCall &c) {
@@ -490,7 +500,6 @@ int launch_force(nbody_ctx *ctx, const ForceCall &c) {
     const int64_t bi = 64 * sh.it;
     int64_t items, need_part;
     if (dev_count) {
-        need_part = 2 * (int64_t)sh.target_groups * bi * 7 * (int64_t)sizeof(double);
         // Upper bound of nb * S over every block size up to n_i_cap, so that
         // each item gets its own workgroup (dispatch order = item order, which
         // keeps the concurrently running groups on one or two j chunks).
@@ -506,6 +515,10 @@ int launch_force(nbody_ctx *ctx, const ForceCall &c) {
         if (b2 > nb_max * smax) b2 = nb_max * smax;
         if (b2 > items) items = b2;
         if (nb_max > items) items = nb_max;
+        // S * n_i <= S * nb * bi <= items * bi, and <= 2 * target_groups * bi
+        // (S > 1 only while nb < target_groups)
+        const int64_t part_rows = std::min<int64_t>(2 * tg, items) * bi;
+        need_part = part_rows * 7 * (int64_t)sizeof(double);
         if (items > (1 << 24)) items = 1 << 24;
     } else {
         int64_t S = choose_splits(c.n_i, c.n_j, sh.it, sh.waves, sh.min_j_wave,

@@ -57,3 +57,20 @@ def test_active_sets_and_configs():
     assert a.dtype == np.int32 and np.all(np.diff(a) > 0)
     assert CONFIGS["plummer1m"].n == 1 << 20
     assert CONFIGS["plummer1k"].eps2 == (1 / 256) ** 2
+
+
+def test_table_protocol_config():
+    from workloads.plummer import CONFIGS, table_protocol_seed
+    cfg = CONFIGS["table_protocol"]
+    assert cfg.extra["n_list"][0] == 256 and cfg.extra["n_list"][-1] == 524288
+    assert cfg.eps == 1.0 / 256 and cfg.dt_max == 0.125 and cfg.t_end == 0.5
+    assert cfg.extra["timed_from"] == 0.25
+    seeds = [table_protocol_seed(n) for n in cfg.extra["n_list"]]
+    assert len(set(seeds)) == len(seeds)
+
+
+def test_power_law_fit_recovers_exact_law():
+    import bench
+    x = [256 << k for k in range(8)]
+    c, p = bench.fit_power_law(x, [0.2 * v ** 0.81 for v in x])
+    assert abs(c - 0.2) < 1e-9 and abs(p - 0.81) < 1e-12

@@ -132,10 +132,22 @@ CONFIGS = {
     "plummer1m": Config("plummer1m", 1 << 20, 1.0 / 4096, 1003,
                         extra={"n_i": (1024, 16384, 262144, 1 << 20),
                                "n_sample": 4096}),
+    # Beyond 2^20: N = 9,000,000 (the paper's capacity claim for its GPU),
+    # force-only on seeded active subsets; N = 2^22, a few block steps.
+    "plummer9m": Config("plummer9m", 9_000_000, 1.0 / 4096, 1007,
+                        extra={"n_i": (1024, 65536), "n_sample": 1024}),
+    "plummer4m": Config("plummer4m", 1 << 22, 1.0 / 4096, 1008,
+                        extra={"steps": 3, "n_sample": 1024}),
     # 256 clusters, N log-uniform in [256, 8192], eps = N^(-1/3)/16, to t=1/16.
     "ensemble256": Config("ensemble256", 0, 0.0, 1004, dt_max=1.0 / 16,
                           t_end=1.0 / 16,
                           extra={"n_clusters": 256, "n_lo": 256, "n_hi": 8192}),
+    # Section 4 results-table protocol: Plummer N = 256 ... 524288 (one
+    # realisation per N), eps = 1/256, dt_max = 1/8, run t: 0 -> 1/2, timed
+    # over t: 1/4 -> 1/2.
+    "table_protocol": Config("table_protocol", 0, 1.0 / 256, 1006, t_end=0.5,
+                             extra={"n_list": tuple(256 << k for k in range(12)),
+                                    "timed_from": 0.25}),
     # Differentiable run: N=16384, eps=1/512, 64 shared steps of 1/512.
     "grad16k": Config("grad16k", 16384, 1.0 / 512, 1005,
                       extra={"dt": 1.0 / 512, "steps": 64, "ckpt": 8,
@@ -143,6 +155,11 @@ CONFIGS = {
                              "n_coords": 32, "target_sigma": 1e-3,
                              "fd_h": 1e-6}),
 }
+
+
+def table_protocol_seed(n: int, cfg: Config = CONFIGS["table_protocol"]) -> int:
+    """Seed of the one realisation used for N particles in the table protocol."""
+    return cfg.seed * 1000 + int(n).bit_length() - 1
 
 
 def ensemble_members(cfg: Config = CONFIGS["ensemble256"]):
