@@ -57,6 +57,8 @@ def _L():
         I = ctypes.c_int
         lib.oracle_force.argtypes = [I64, P, I64, P, P, P, D, P, P, P]
         lib.oracle_force.restype = None
+        lib.oracle_force_sum32.argtypes = [I64, P, I64, P, P, P, D, I, P, P, P]
+        lib.oracle_force_sum32.restype = I
         lib.oracle_predict.argtypes = [I64, D, P, P, P, P, P, P, P]
         lib.oracle_predict.restype = None
         lib.oracle_schedule.argtypes = [I64, P, P, P, P]
@@ -121,6 +123,32 @@ def force(pos, vel, mass, eps2, active=None):
     pot = np.empty(n_i)
     _L().oracle_force(n_i, None if act is None else _p(act), n_j, _p(pos),
                       _p(vel), _p(mass), float(eps2), _p(acc), _p(jerk), _p(pot))
+    return acc, jerk, pot
+
+
+def force_sum32(pos, vel, mass, eps2, active=None, order="sorted"):
+    """The pair sums of force(), each term rounded to float32 and added in
+    float32 in ascending j (order="index") or smallest force first
+    (order="sorted", the summation order Section 6 proposes).
+
+    Returns (acc (3, n_i), jerk (3, n_i), pot (n_i,)) as float64 arrays
+    holding the float32 sums.
+    """
+    pos, vel, mass = _f64(pos), _f64(vel), _f64(mass)
+    n_j = mass.shape[0]
+    if active is None:
+        n_i, act = n_j, None
+    else:
+        act = np.ascontiguousarray(active, dtype=np.int32)
+        n_i = act.shape[0]
+    acc = np.empty((3, n_i))
+    jerk = np.empty((3, n_i))
+    pot = np.empty(n_i)
+    code = {"index": 0, "sorted": 1}[order]
+    rc = _L().oracle_force_sum32(n_i, None if act is None else _p(act), n_j, _p(pos), _p(vel),
+                                 _p(mass), float(eps2), code, _p(acc), _p(jerk), _p(pot))
+    if rc != 0:
+        raise MemoryError("oracle_force_sum32: out of memory")
     return acc, jerk, pot
 
 

@@ -112,6 +112,96 @@ void oracle_force(int64_t n_i, const int32_t *active, int64_t n_j,
 }
 
 /* ------------------------------------------------------------------------
+ * Pair sums accumulated in float32, in index order or smallest force first.
+ *
+ * Section 6 notes that the accuracy of single-precision sums could be
+ * improved by sorting the forces by size and adding the smallest first.
+ * This is that arithmetic, written out: for each i every pair term of the
+ * sums above is evaluated in float64 and rounded once to float32; the terms
+ * are then added in float32, one after the other, either in ascending j
+ * (order 0) or in ascending size of the pair force m_j |r| / s^(3/2)
+ * (order 1; ties by j), the same order for all seven sums.  Outputs are the
+ * float32 sums widened to float64, indexed by slot as in oracle_force.
+ * ---------------------------------------------------------------------- */
+typedef struct {
+    double key;
+    int64_t j;
+} SizeKey;
+
+static int cmp_size(const void *pa, const void *pb)
+{
+    const SizeKey *a = (const SizeKey *)pa, *b = (const SizeKey *)pb;
+    if (a->key < b->key) return -1;
+    if (a->key > b->key) return 1;
+    return (a->j > b->j) - (a->j < b->j);
+}
+
+int oracle_force_sum32(int64_t n_i, const int32_t *active, int64_t n_j,
+                       const double *pos, const double *vel, const double *mass,
+                       double eps2, int order, double *acc, double *jerk,
+                       double *pot)
+{
+    int fail = 0;
+#pragma omp parallel
+    {
+        float *term = (float *)malloc(sizeof(float) * 7 * (size_t)(n_j > 0 ? n_j : 1));
+        SizeKey *keys = (SizeKey *)malloc(sizeof(SizeKey) * (size_t)(n_j > 0 ? n_j : 1));
+        int64_t s;
+        if (!term || !keys) {
+#pragma omp atomic write
+            fail = 1;
+        }
+#pragma omp for schedule(dynamic, 1)
+        for (s = 0; s < n_i; ++s) {
+            const int64_t i = active ? (int64_t)active[s] : s;
+            const double xi = pos[i], yi = pos[n_j + i], zi = pos[2 * n_j + i];
+            const double ui = vel[i], vi = vel[n_j + i], wi = vel[2 * n_j + i];
+            float sum[7] = {0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
+            int64_t j, m = 0, q;
+            int c;
+            if (!term || !keys) continue;
+            for (j = 0; j < n_j; ++j) {
+                double rx, ry, rz, vx, vy, vz, s2, rv, rinv, r3inv, r5inv, mj;
+                if (j == i) continue;
+                rx = pos[j] - xi;
+                ry = pos[n_j + j] - yi;
+                rz = pos[2 * n_j + j] - zi;
+                vx = vel[j] - ui;
+                vy = vel[n_j + j] - vi;
+                vz = vel[2 * n_j + j] - wi;
+                s2 = rx * rx + ry * ry + rz * rz + eps2;
+                rv = rx * vx + ry * vy + rz * vz;
+                rinv = 1.0 / sqrt(s2);
+                r3inv = rinv * rinv * rinv;
+                r5inv = r3inv * rinv * rinv;
+                mj = mass[j];
+                term[7 * m + 0] = (float)(mj * rx * r3inv);
+                term[7 * m + 1] = (float)(mj * ry * r3inv);
+                term[7 * m + 2] = (float)(mj * rz * r3inv);
+                term[7 * m + 3] = (float)(mj * (vx * r3inv - 3.0 * rv * rx * r5inv));
+                term[7 * m + 4] = (float)(mj * (vy * r3inv - 3.0 * rv * ry * r5inv));
+                term[7 * m + 5] = (float)(mj * (vz * r3inv - 3.0 * rv * rz * r5inv));
+                term[7 * m + 6] = (float)(-mj * rinv);
+                keys[m].key = fabs(mj) * sqrt(rx * rx + ry * ry + rz * rz) * r3inv;
+                keys[m].j = m;
+                ++m;
+            }
+            if (order == 1) qsort(keys, (size_t)m, sizeof(SizeKey), cmp_size);
+            for (q = 0; q < m; ++q) {
+                const int64_t t = (order == 1) ? keys[q].j : q;
+                for (c = 0; c < 7; ++c) sum[c] = sum[c] + term[7 * t + c];
+            }
+            acc[s] = sum[0]; acc[n_i + s] = sum[1]; acc[2 * n_i + s] = sum[2];
+            jerk[s] = sum[3]; jerk[n_i + s] = sum[4]; jerk[2 * n_i + s] = sum[5];
+            pot[s] = sum[6];
+        }
+        free(term);
+        free(keys);
+    }
+    return fail ? ORC_E_INVAL : ORC_OK;
+}
+
+/* ------------------------------------------------------------------------
  * Predictor (Section 2): with dt = t_target - t_i,
  *     x_p = x + (v + (dt/2) (a + (dt/3) k)) dt
  *     v_p = v + (a + (dt/2) k) dt

@@ -1,0 +1,53 @@
+"""Accuracy of the summation modes against the float64 oracle (Section 6).
+
+The paper proposes adding the pair forces smallest first to improve its
+float32 sums.  The oracle writes that arithmetic out (float32 terms,
+smallest force first, float32 running sum) next to the plain float32
+running sum in index order.  On the same sampled i-particles of the
+Plummer N = 65536 and N = 2^20 workloads, the GPU's float32 mode (float32
+tile sums of 128 terms folded into a float32 total per split, splits added
+in float64) and its compensated mode are compared with them.  Gates: the
+ordering of the acceleration errors at the 99th percentile,
+  GPU compensated <= GPU float32 < sorted float32 < index-order float32
+(the first within 5 %: at N = 65536 both GPU modes sit on the float32
+pair-arithmetic floor), i.e. the GPU's blocked sums already beat the
+paper's proposal.
+"""
+import numpy as np
+import pytest
+
+from tests.gpu_util import dev, host, need_gpu, say
+from workloads.plummer import CONFIGS, plummer, random_active_set
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.mark.parametrize("name,n_s", [("plummer64k", 256), ("plummer1m", 64)])
+def test_summation_modes_accuracy_order(orc, name, n_s):
+    need_gpu()
+    import paper_cs_0702135_amd as nb
+    import torch
+    cfg = CONFIGS[name]
+    pos, vel, m = plummer(cfg.n, cfg.seed)
+    act = random_active_set(cfg.n, n_s, cfg.seed + 99)
+    ra, rk, rp = orc.force(pos, vel, m, cfg.eps2, active=act)
+
+    def p99(a, k):
+        ea = np.linalg.norm(a - ra, axis=0) / np.linalg.norm(ra, axis=0)
+        ek = np.linalg.norm(k - rk, axis=0) / np.linalg.norm(rk, axis=0)
+        return np.percentile(ea, 99), np.percentile(ek, 99)
+
+    res = {}
+    for order in ("index", "sorted"):
+        a, k, _ = orc.force_sum32(pos, vel, m, cfg.eps2, active=act, order=order)
+        res["oracle float32 " + order] = p99(a, k)
+    P, V, M, A = dev(pos), dev(vel), dev(m), dev(act, torch.int32)
+    for mode in ("fp32", "ds"):
+        a, k, _ = nb.force(P, V, M, cfg.eps2, A, mode)
+        res["GPU " + mode] = p99(host(a), host(k))
+    for key, (ea, ek) in res.items():
+        say("%s N=%d %-22s acc p99 %.2e  jerk p99 %.2e" % (name, cfg.n, key, ea, ek))
+    acc = {key: v[0] for key, v in res.items()}
+    # (at N = 65536 both GPU modes sit on the float32 pair-arithmetic floor)
+    assert acc["GPU ds"] <= 1.05 * acc["GPU fp32"]
+    assert acc["GPU fp32"] < acc["oracle float32 sorted"] < acc["oracle float32 index"]

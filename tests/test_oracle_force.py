@@ -135,3 +135,92 @@ def test_self_pair_excluded_by_index(orc):
     pos, vel, m, om, s = _binary(0.5, 0.5, 1.0, 0.0)
     acc, jerk, pot = orc.force(pos, vel, m, 0.0)
     assert np.isfinite(acc).all() and np.isfinite(pot).all()
+
+
+# ---- float32 sums in index order and smallest force first (Section 6) ----
+
+def test_sum32_single_term_is_rounded_exact_term(orc):
+    # two particles: each sum has one term, so both orders give the float32
+    # rounding of the float64 term
+    pos = np.array([[0.0, 0.3], [0.0, -0.2], [0.0, 0.1]])
+    vel = np.array([[0.1, -0.05], [0.0, 0.2], [0.3, 0.0]])
+    m = np.array([0.25, 0.75])
+    ra, rk, rp = orc.force(pos, vel, m, 1e-3)
+    for order in ("index", "sorted"):
+        a, k, p = orc.force_sum32(pos, vel, m, 1e-3, order=order)
+        np.testing.assert_array_equal(a, ra.astype(np.float32).astype(np.float64))
+        np.testing.assert_array_equal(k, rk.astype(np.float32).astype(np.float64))
+        np.testing.assert_array_equal(p, rp.astype(np.float32).astype(np.float64))
+
+
+def test_sorted_sum32_keeps_small_forces_that_index_order_drops(orc):
+    # particle 0 at the origin, particle 1 close by (one large force), then
+    # 4000 distant particles whose forces are each below half an ulp of the
+    # large one: added after it in index order they are all lost; added
+    # first (smallest first) they survive, so the sorted float32 sum is
+    # within an ulp of the float64 sum.
+    k = 4000
+    x = np.zeros((3, k + 2))
+    x[0, 1] = 0.01
+    rng = np.random.default_rng(5)
+    x[0, 2:] = 100.0 + rng.uniform(0, 1, k)
+    m = np.full(k + 2, 1e-3)
+    v = np.zeros_like(x)
+    ra, _, _ = orc.force(x, v, m, 0.0, active=np.array([0], np.int32))
+    ai, _, _ = orc.force_sum32(x, v, m, 0.0, active=np.array([0], np.int32), order="index")
+    asd, _, _ = orc.force_sum32(x, v, m, 0.0, active=np.array([0], np.int32), order="sorted")
+    exact = ra[0, 0]
+    ulp = np.spacing(np.float32(exact))
+    assert abs(asd[0, 0] - exact) <= ulp
+    assert abs(ai[0, 0] - exact) > 100 * ulp
+    # the index-order float32 sum equals the large term alone
+    assert ai[0, 0] == float(np.float32(np.float32(1e-3 / 0.01 ** 2)))
+
+
+def test_sorted_sum32_does_not_depend_on_particle_order(orc):
+    pos, vel, m = plummer(700, 41)
+    m = m * (1.0 + 0.5 * np.random.default_rng(42).uniform(size=m.shape))  # distinct keys
+    perm = np.random.default_rng(43).permutation(700)
+    a0, k0, p0 = orc.force_sum32(pos, vel, m, 1e-4, order="sorted")
+    a1, k1, p1 = orc.force_sum32(pos[:, perm], vel[:, perm], m[perm], 1e-4, order="sorted")
+    inv = np.argsort(perm)
+    np.testing.assert_array_equal(a1[:, inv], a0)
+    np.testing.assert_array_equal(k1[:, inv], k0)
+    np.testing.assert_array_equal(p1[inv], p0)
+    # index order does depend on it (float32 addition is not associative)
+    b0 = orc.force_sum32(pos, vel, m, 1e-4, order="index")[0]
+    b1 = orc.force_sum32(pos[:, perm], vel[:, perm], m[perm], 1e-4, order="index")[0]
+    assert not np.array_equal(b1[:, inv], b0)
+
+
+def test_sum32_orders_close_to_float64_sum(orc):
+    # both float32 sums stay within float32 accumulation error of the exact
+    # sum on a small Plummer sphere
+    pos, vel, m = plummer(2048, 44)
+    ra, _, _ = orc.force(pos, vel, m, 1e-4)
+    for order in ("index", "sorted"):
+        a, _, _ = orc.force_sum32(pos, vel, m, 1e-4, order=order)
+        err = np.linalg.norm(a - ra, axis=0) / np.linalg.norm(ra, axis=0)
+        assert np.percentile(err, 99) < 2e-5
+
+
+def test_sorted_sum32_orders_by_force_not_distance(orc):
+    # particle 0 at the origin; a massive distant particle (m = 1e4 at
+    # x = 100) and a light near one (m = 1 at x = -1) pull with forces +1
+    # and -1; 1000 particles at x ~ 10 add 4e-8 each (4e-5 in all), each
+    # below half an ulp of 1.  Smallest force first, the 4e-5 is summed
+    # before the two unit forces and survives their cancellation; ordered
+    # by distance instead, the far unit force would come first and swallow
+    # every small term.
+    k = 1000
+    x = np.zeros((3, k + 3))
+    x[0, 1], x[0, 2] = 100.0, -1.0
+    x[0, 3:] = 10.0 + np.random.default_rng(6).uniform(0, 1e-3, k)
+    m = np.full(k + 3, 4e-6)
+    m[1], m[2] = 1e4, 1.0
+    v = np.zeros_like(x)
+    one = np.array([0], np.int32)
+    exact = orc.force(x, v, m, 0.0, active=one)[0][0, 0]
+    got = orc.force_sum32(x, v, m, 0.0, active=one, order="sorted")[0][0, 0]
+    assert 3.9e-5 < exact < 4.1e-5
+    assert abs(got - exact) <= 1e-2 * exact

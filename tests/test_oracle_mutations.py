@@ -55,6 +55,12 @@ MUTATIONS = [
     ("adjoint_velocity_term", "gv[c] = mj * (al * K[c] - 3.0 * be * kr * r[c]);",
      "gv[c] = mj * (al * K[c]);",
      lambda o: T_adj.test_dot_product_identity(o, 0.0)),
+    ("sorted_largest_first", "if (a->key < b->key) return -1;", "if (a->key > b->key) return -1;",
+     T_force.test_sorted_sum32_keeps_small_forces_that_index_order_drops),
+    ("sum32_in_float64", "float sum[7] = {", "double sum[7] = {",
+     T_force.test_sorted_sum32_keeps_small_forces_that_index_order_drops),
+    ("sorted_key_ignores_mass", "keys[m].key = fabs(mj) * sqrt", "keys[m].key = sqrt",
+     T_force.test_sorted_sum32_orders_by_force_not_distance),
 ]
 
 
