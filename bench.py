@@ -64,6 +64,61 @@ def fit_power_law(x, y):
     return float(np.exp(lc)), float(p)
 
 
+def ensemble_only(args):
+    """The batched-ensemble workload alone: 256 Plummer clusters (N
+    log-uniform in [256, 8192], eps = N^(-1/3)/16, seed 1004) integrated to
+    t = 1/16 in one persistent launch; a warm-up launch, then `steps` timed
+    launches.  Prints one JSON line with the block interactions per second
+    and the launch's float32 roofline (60 flops per interaction)."""
+    import numpy as np
+    import torch
+
+    import paper_cs_0702135_amd as nb
+    from paper_cs_0702135_amd import autotune
+    from workloads.plummer import CONFIGS, ensemble_members, plummer
+
+    ce = CONFIGS["ensemble256"]
+    sizes, eps_c, seeds = ensemble_members(ce)
+    parts = [plummer(int(nc), int(sd)) for nc, sd in zip(sizes, seeds)]
+    EP = torch.from_numpy(np.concatenate([q[0] for q in parts], axis=1)).cuda()
+    EV = torch.from_numpy(np.concatenate([q[1] for q in parts], axis=1)).cuda()
+    EM = torch.from_numpy(np.concatenate([q[2] for q in parts])).cuda()
+    off = np.concatenate([[0], np.cumsum(sizes)]).astype(np.int64)
+    cfg = autotune.load_or_calibrate_ensemble(args.mode, log=log)
+    for _ in range(max(1, args.warmup)):
+        nb.ensemble_run(EP, EV, EM, off, eps_c ** 2, ce.t_end, dt_max=ce.dt_max, mode=args.mode)
+    torch.cuda.synchronize()
+    inter, secs = 0, 0.0
+    for _ in range(args.steps):
+        ta = time.perf_counter()
+        res = nb.ensemble_run(EP, EV, EM, off, eps_c ** 2, ce.t_end, dt_max=ce.dt_max,
+                              mode=args.mode)
+        secs += time.perf_counter() - ta
+        inter += sum(res["interactions"])
+    achieved = FLOPS_PER_INTERACTION * inter / secs / 1e12
+    out = {
+        "metric": "block pair interactions/s of the batched ensemble (one persistent launch)",
+        "value": inter / secs,
+        "unit": "interactions/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": secs / args.steps * 1e3,
+        "higher_is_better": True,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "256 Plummer clusters, N log-uniform in [256, 8192], "
+                               "eps = N^(-1/3)/16, eta = 0.02, dt_max = 1/16, t: 0 -> 1/16",
+                   "accumulation": args.mode, "grid_teams": list(nb.ensemble_info()),
+                   "model": cfg},
+        "roofline": {"bound": "alu", "kernel": "ensemble_kernel", "achieved": round(achieved, 2),
+                     "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
+                     "frac": round(achieved / FP32_PEAK_TFLOPS, 4),
+                     "flops_per_interaction": FLOPS_PER_INTERACTION},
+    }
+    print(json.dumps(out), flush=True)
+
+
 def paper_table(args):
     """The Section 4 results-table protocol on one GPU: for each N, one
     seeded Plummer realisation, eps = 1/256, eta = 0.02, dt_max = 1/8,
@@ -168,6 +223,8 @@ def main():
     ap.add_argument("--retune", action="store_true")
     ap.add_argument("--paper-table", action="store_true",
                     help="run the Section 4 results-table protocol instead of the default step")
+    ap.add_argument("--ensemble", action="store_true",
+                    help="run only the batched-ensemble workload")
     ap.add_argument("--table-max-n", type=int, default=1 << 19,
                     help="largest N of the results-table protocol")
     ap.add_argument("--calib-copy", action="store_true",
@@ -192,6 +249,9 @@ def main():
 
     if args.paper_table:
         paper_table(args)
+        return
+    if args.ensemble:
+        ensemble_only(args)
         return
 
     import numpy as np

@@ -256,6 +256,23 @@ int nbody_ensemble_timing(nbody_ctx *ctx, int32_t n_clusters, double *seconds,
 /* Grid size and number of teams of the last ensemble launch (HOST outputs). */
 int nbody_ensemble_info(nbody_ctx *ctx, int32_t *grid, int32_t *teams);
 
+/* The team plan nbody_ensemble_run would use, computed on the host only (no
+ * context, no device): the same planner, for a grid of `groups` workgroups.
+ *   sizes         : HOST int64[n_clusters], particles per cluster (>= 1).
+ *   cfg           : the planning model, as nbody_ensemble_set takes it.
+ *   t_end         : end time the model's step count scales with (>= 0).
+ *   team_of       : HOST int32[n_clusters] output, team of each cluster.
+ *   team_size     : HOST int32[n_clusters] output, groups of team q for
+ *                   q < *n_teams (there are never more teams than clusters).
+ *   model_seconds : HOST float64[n_clusters] output (may be NULL), modelled
+ *                   time of each cluster on its team.
+ *   n_teams       : HOST output.
+ * Returns NBODY_E_INVAL on null pointers, n_clusters < 1, groups < 1, a
+ * cluster size < 1 or a model with non-positive rates. */
+int nbody_ensemble_plan(const int64_t *sizes, int32_t n_clusters, int32_t groups,
+                        const nbody_ensemble_config *cfg, double t_end, int32_t *team_of,
+                        int32_t *team_size, double *model_seconds, int32_t *n_teams);
+
 /* ---- adjoint (not in the paper: the transpose of the pair sums above) ----
  * For the full set (every particle is both i and j, n_i = n_j = n) and
  * cotangents abar, kbar, pbar of acc, jerk, pot, writes

@@ -254,7 +254,8 @@ static double norm3(const double *q, int64_t n, int64_t i)
 }
 
 /* Initial step: eta_s |a| / |k|, floored to a power of two not above dt_max,
- * halved until t0 is a multiple of it. */
+ * halved until t0 is a multiple of it.  A non-finite |a| or |k| carries no
+ * step information: the particle gets dt_min and the call reports it. */
 int oracle_initial_dt(int64_t n, double t0, const double *a, const double *k,
                       double eta_s, double dt_max, double dt_min, double *dt)
 {
@@ -265,7 +266,10 @@ int oracle_initial_dt(int64_t n, double t0, const double *a, const double *k,
         double want, d;
         if (kn > 0.0) want = eta_s * an / kn;
         else want = dt_max;
-        if (!(want == want)) { rc = ORC_E_NONFINITE; want = dt_min; }
+        if (!(want == want) || !isfinite(an) || !isfinite(kn)) {
+            rc = ORC_E_NONFINITE;
+            want = dt_min;
+        }
         d = dt_max;
         while (d > want && d >= 2.0 * dt_min) d = d / 2.0;
         while (fmod(t0, d) != 0.0 && d >= 2.0 * dt_min) d = d / 2.0;
@@ -310,7 +314,7 @@ int oracle_correct(int64_t n, int64_t n_i, const int32_t *active,
         const double h = dt[i];
         const double t_new = t[i] + h;
         double a2v[3], a3v[3], a1v[3], k1v[3];
-        int c;
+        int c, bad = 0;
         for (c = 0; c < 3; ++c) {
             const int64_t q = c * n + i;
             const double a0 = a[q], k0 = k[q];
@@ -325,8 +329,11 @@ int oracle_correct(int64_t n, int64_t n_i, const int32_t *active,
             k1v[c] = k1;
             a2v[c] = (2.0 * A2 + 6.0 * A3) / (h * h);
             a3v[c] = 6.0 * A3 / (h * h * h);
+            if (!isfinite(x[q]) || !isfinite(v[q]) || !isfinite(a1) || !isfinite(k1)) bad = 1;
         }
         t[i] = t_new;
+        /* a non-finite corrected state is reported and keeps its step */
+        if (bad) rc = ORC_E_NONFINITE;
         if (!fixed_dt) {
             const double an = sqrt(a1v[0] * a1v[0] + a1v[1] * a1v[1] + a1v[2] * a1v[2]);
             const double kn = sqrt(k1v[0] * k1v[0] + k1v[1] * k1v[1] + k1v[2] * k1v[2]);
@@ -337,7 +344,7 @@ int oracle_correct(int64_t n, int64_t n_i, const int32_t *active,
             double crit, d = h;
             if (den > 0.0) crit = sqrt(num / den);
             else crit = INFINITY;
-            if (!(crit == crit)) { rc = ORC_E_NONFINITE; crit = d; }
+            if (bad || !(crit == crit)) { rc = ORC_E_NONFINITE; crit = d; }
             if (d > crit) {
                 while (d > crit) d = d / 2.0;
             } else if (2.0 * d <= crit && fmod(t_new, 2.0 * d) == 0.0 &&

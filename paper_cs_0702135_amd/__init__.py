@@ -26,7 +26,7 @@ __all__ = [
     "correct", "initial_dt", "energy", "System", "ACC_FP32", "ACC_DS",
     "ForceShape", "tune_set", "tune_clear", "tune_get", "profile",
     "force_adjoint", "predict_adjoint", "correct_adjoint", "ensemble_run",
-    "ensemble_set", "ensemble_get", "ensemble_info", "ensemble_timing",
+    "ensemble_set", "ensemble_get", "ensemble_info", "ensemble_timing", "ensemble_plan",
 ]
 
 ACC_FP32 = L.NBODY_ACC_FP32
@@ -327,6 +327,36 @@ def ensemble_info(device=None):
     g, t = ctypes.c_int32(), ctypes.c_int32()
     ctx.check(ctx.lib.nbody_ensemble_info(ctx.h, ctypes.byref(g), ctypes.byref(t)))
     return g.value, t.value
+
+
+def ensemble_plan(sizes, groups, t_end, config):
+    """Team plan of the ensemble for cluster `sizes` on a grid of `groups`
+    workgroups under the planning model `config` (a dict with the fields of
+    nbody_ensemble_config), computed on the host (nbody_ensemble_plan).
+
+    Returns (team_of (n_clusters,), team_size (n_teams,), model_seconds
+    (n_clusters,)) as numpy arrays.
+    """
+    import numpy as _np
+    sz = _np.ascontiguousarray(sizes, dtype=_np.int64)
+    nc = sz.shape[0]
+    cfg = L.NBodyEnsembleConfig(int(config["groups_per_cu"]), int(config["max_team"]),
+                                float(config["step_us"]), float(config["barrier_us"]),
+                                float(config["barrier_group_us"]), float(config["group_rate"]),
+                                float(config["steps_coef"]), float(config["steps_exp"]))
+    team_of = _np.empty(nc, dtype=_np.int32)
+    team_size = _np.empty(nc, dtype=_np.int32)
+    secs = _np.empty(nc, dtype=_np.float64)
+    nt = ctypes.c_int32()
+    lib = L.load()
+    rc = lib.nbody_ensemble_plan(sz.ctypes.data_as(ctypes.c_void_p), nc, int(groups),
+                                 ctypes.byref(cfg), float(t_end),
+                                 team_of.ctypes.data_as(ctypes.c_void_p),
+                                 team_size.ctypes.data_as(ctypes.c_void_p),
+                                 secs.ctypes.data_as(ctypes.c_void_p), ctypes.byref(nt))
+    if rc != 0:
+        raise NBodyError(rc, "nbody_ensemble_plan: bad arguments")
+    return team_of, team_size[:nt.value].copy(), secs
 
 
 class ForceShape(tuple):

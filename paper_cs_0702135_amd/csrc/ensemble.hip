@@ -763,6 +763,33 @@ static Plan plan_teams(const std::vector<int64_t> &sizes, int G, int max_team,
 
 using namespace nb;
 
+extern "C" int nbody_ensemble_plan(const int64_t *sizes, int32_t n_clusters, int32_t groups,
+                                   const nbody_ensemble_config *cfg, double t_end,
+                                   int32_t *team_of, int32_t *team_size, double *model_seconds,
+                                   int32_t *n_teams) {
+    if (!sizes || !cfg || !team_of || !team_size || !n_teams || n_clusters < 1 || groups < 1 ||
+        !(t_end >= 0.0) || !(cfg->group_rate > 0.0) || !(cfg->steps_coef > 0.0) ||
+        cfg->max_team < 1)
+        return NBODY_E_INVAL;
+    std::vector<int64_t> sz(sizes, sizes + n_clusters);
+    for (int64_t v : sz)
+        if (v < 1) return NBODY_E_INVAL;
+    TimeModel M{cfg->step_us * 1e-6, cfg->barrier_us * 1e-6, cfg->barrier_group_us * 1e-6,
+                cfg->group_rate,     t_end,               cfg->steps_coef, cfg->steps_exp};
+    Plan P = plan_teams(sz, groups, std::min(cfg->max_team, 64), M);
+    for (int q = 0; q < (int)P.teams.size(); ++q) {
+        const EnsTeam &T = P.teams[q];
+        team_size[q] = T.size;
+        for (int r = T.cl_begin; r < T.cl_end; ++r) {
+            const int c = P.order[r];
+            team_of[c] = q;
+            if (model_seconds) model_seconds[c] = M.time((double)sz[c], T.size);
+        }
+    }
+    *n_teams = (int32_t)P.teams.size();
+    return NBODY_OK;
+}
+
 extern "C" int nbody_ensemble_run(nbody_ctx *ctx, const nbody_ensemble *e, double t_end,
                                   int64_t *steps, int64_t *interactions) {
     if (!ctx) return NBODY_E_INVAL;

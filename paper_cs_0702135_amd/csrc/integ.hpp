@@ -49,6 +49,7 @@ __device__ __forceinline__ int32_t correct_vals(int64_t q, int64_t cs, const dou
     const double h = dtv[q];
     const double t_new = t[q] + h;
     double a2v[3], a3v[3];
+    bool bad = false;
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
         const int64_t e = q + c * cs;
@@ -56,14 +57,19 @@ __device__ __forceinline__ int32_t correct_vals(int64_t q, int64_t cs, const dou
         const double a1 = a1v[c], k1 = k1v[c];
         const double A3 = 2.0 * (a0 - a1) + (k0 + k1) * h;
         const double A2 = -3.0 * (a0 - a1) - (2.0 * k0 + k1) * h;
-        x[e] = xp[c] + (A2 / 12.0 + A3 / 20.0) * h * h;
-        v[e] = vp[c] + (A2 / 3.0 + A3 / 4.0) * h;
+        const double xn = xp[c] + (A2 / 12.0 + A3 / 20.0) * h * h;
+        const double vn = vp[c] + (A2 / 3.0 + A3 / 4.0) * h;
+        x[e] = xn;
+        v[e] = vn;
         a[e] = a1;
         k[e] = k1;
         a2v[c] = (2.0 * A2 + 6.0 * A3) / (h * h);
         a3v[c] = 6.0 * A3 / (h * h * h);
+        bad = bad || !isfinite(xn) || !isfinite(vn) || !isfinite(a1) || !isfinite(k1);
     }
     t[q] = t_new;
+    // a non-finite corrected state is reported and keeps its step
+    if (bad) st |= ST_NONFINITE;
     if (!fixed_dt) {
         const double an = sqrt(a1v[0] * a1v[0] + a1v[1] * a1v[1] + a1v[2] * a1v[2]);
         const double kn = sqrt(k1v[0] * k1v[0] + k1v[1] * k1v[1] + k1v[2] * k1v[2]);
@@ -73,7 +79,7 @@ __device__ __forceinline__ int32_t correct_vals(int64_t q, int64_t cs, const dou
         const double den = kn * a3n + a2n * a2n;
         double crit = den > 0.0 ? sqrt(num / den) : INFINITY;
         double d = h;
-        if (!(crit == crit)) {
+        if (bad || !(crit == crit)) {
             st |= ST_NONFINITE;
             crit = d;
         }
@@ -118,7 +124,8 @@ __device__ __forceinline__ double initial_dt_one(int64_t q, int64_t cs, double t
     const double an = sqrt(ax * ax + ay * ay + az * az);
     const double kn = sqrt(kx * kx + ky * ky + kz * kz);
     double want = kn > 0.0 ? eta_s * an / kn : dt_max;
-    if (!(want == want)) {
+    // a non-finite norm carries no step information
+    if (!(want == want) || !isfinite(an) || !isfinite(kn)) {
         *st |= ST_NONFINITE;
         want = dt_min;
     }

@@ -166,6 +166,40 @@ def test_initial_step_power_of_two(orc):
     assert rc == 0 and np.all(np.fmod(0.375, dt2) == 0)
 
 
+def test_initial_step_flags_nonfinite_norms(orc):
+    # a NaN or infinite |a| or |k| gives no step: dt_min, reported; zero
+    # jerk alone is finite and sets no limit (dt_max)
+    a = np.ones((3, 4))
+    k = np.ones((3, 4))
+    k[1, 0] = np.nan
+    a[2, 1] = np.inf
+    k[:, 2] = 0.0
+    dt, rc = orc.initial_dt(0.0, a, k, 0.01, 0.125, 2.0 ** -40)
+    assert rc == orc.E_NONFINITE
+    assert dt[0] == 2.0 ** -40 and dt[1] == 2.0 ** -40
+    assert dt[2] == 0.125
+    e = np.log2(dt[3])
+    assert e == np.round(e) and dt[3] <= 0.01
+
+
+@pytest.mark.parametrize("fixed_dt", [False, True])
+def test_corrector_reports_nonfinite_state(orc, fixed_dt):
+    # a NaN in the new force of one particle: reported, its step kept; the
+    # other particle is corrected as usual
+    n = 2
+    rng = np.random.default_rng(12)
+    x, v, a, k = (rng.normal(size=(3, n)) for _ in range(4))
+    t = np.zeros(n)
+    dt = np.full(n, 1.0 / 64)
+    an, kn = rng.normal(size=(3, n)), rng.normal(size=(3, n))
+    an[1, 0] = np.nan
+    rc = orc.correct(None, x.copy(), v.copy(), an, kn, 0.02, 0.125, 2.0 ** -40, t, dt, x, v, a,
+                     k, fixed_dt=fixed_dt)
+    assert rc == orc.E_NONFINITE
+    assert dt[0] == 1.0 / 64 and np.all(t == 1.0 / 64)
+    assert np.all(np.isfinite(x[:, 1])) and np.all(np.isfinite(v[:, 1]))
+
+
 def test_scheduler_definition(orc):
     rng = np.random.default_rng(10)
     n = 1000

@@ -55,6 +55,10 @@ MUTATIONS = [
     ("adjoint_velocity_term", "gv[c] = mj * (al * K[c] - 3.0 * be * kr * r[c]);",
      "gv[c] = mj * (al * K[c]);",
      lambda o: T_adj.test_dot_product_identity(o, 0.0)),
+    ("initial_step_ignores_nonfinite_norms", "!(want == want) || !isfinite(an) || !isfinite(kn)",
+     "!(want == want)", T_int.test_initial_step_flags_nonfinite_norms),
+    ("corrector_ignores_nonfinite_state", "if (bad) rc = ORC_E_NONFINITE;", "",
+     lambda o: T_int.test_corrector_reports_nonfinite_state(o, True)),
     ("sorted_largest_first", "if (a->key < b->key) return -1;", "if (a->key > b->key) return -1;",
      T_force.test_sorted_sum32_keeps_small_forces_that_index_order_drops),
     ("sum32_in_float64", "float sum[7] = {", "double sum[7] = {",
