@@ -430,29 +430,32 @@ static force_fn pick_kernel(const ForceShape &s, bool ds) {
 }
 
 
-// Built-in shape for an active block of about n_i particles, following what
-// the autotuner finds on the MI355X: blocks below 256 keep one i per lane
-// and four waves splitting j; larger blocks take two i per lane (two
-// independent chains per lane hide the rsq and FMA latencies) and two
-// waves.  The target of 128 groups per CU (32768 in all) makes the j splits
-// small enough for the groups resident on an XCD to share their j chunk
-// in L2.
-static ForceShape default_shape(const nbody_ctx *ctx, int64_t n_i) {
+// Built-in shape for an active block of about n_i particles against n_j,
+// following what the autotuner and the block-step runs find on the MI355X:
+// blocks below 256 keep one i per lane and four waves splitting j; larger
+// blocks take two i per lane (two independent chains per lane hide the rsq
+// and FMA latencies) and two waves.  The target of 128 groups per CU (32768
+// in all) makes the j splits small enough for the groups resident on an
+// XCD to share their j chunk in L2.  Up to n_j = 8192 a wave may take as
+// few as 16 j: a lone wave walking a long chain of scalar j loads is
+// latency-bound, so small systems split j over more workgroups (13-28 %
+// faster block steps at N = 256 ... 8192); beyond, finer splits cost more
+// in partial sums than they hide (64 j per wave).
+static ForceShape default_shape(const nbody_ctx *ctx, int64_t n_i, int64_t n_j) {
     ForceShape s;
     s.rep = REP_F64;
     s.it = n_i >= 256 ? 2 : 1;
     s.waves = n_i >= 1024 ? 2 : 4;
     s.tile = 128;
-    s.min_j_wave = 64;
+    s.min_j_wave = n_j <= 8192 ? 16 : 64;
     s.target_groups = 128 * ctx->cus;
     return s;
 }
 
 ForceShape pick_shape(const nbody_ctx *ctx, int64_t n_i, int64_t n_j) {
-    (void)n_j;
     for (const TuneEntry &e : ctx->tune)
         if (e.n_i_lo >= 0 && n_i >= e.n_i_lo && n_i < e.n_i_hi) return e.shape;
-    return default_shape(ctx, n_i);
+    return default_shape(ctx, n_i, n_j);
 }
 
 // Shape of the block-step launches, whose n_i is only known on the device:
@@ -461,7 +464,7 @@ ForceShape pick_shape(const nbody_ctx *ctx, int64_t n_i, int64_t n_j) {
 ForceShape dynamic_shape(const nbody_ctx *ctx, int64_t n) {
     for (const TuneEntry &e : ctx->tune)
         if (e.n_i_lo < 0) return e.shape;
-    return default_shape(ctx, (int64_t)(0.1 * std::pow((double)n, 0.9)));
+    return default_shape(ctx, (int64_t)(0.1 * std::pow((double)n, 0.9)), n);
 }
 
 int launch_force(nbody_ctx *ctx, const ForceCall &c) {
