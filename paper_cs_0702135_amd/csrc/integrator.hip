@@ -204,6 +204,83 @@ __global__ __launch_bounds__(256) void sched_compact_kernel(int64_t n,
     }
 }
 
+// Small systems (n <= kSmallStep): the whole scheduling part of a block step
+// -- t_next = min(t + dt), the block in ascending order, and the prediction
+// of every particle -- in one workgroup of 1024 threads, i.e. one launch
+// instead of four (each of which costs a few microseconds at this size).
+// Same arithmetic as sched_* and predict_kernel: exact minimum, block-order
+// compaction, the Section 2 predictor.
+constexpr int64_t kSmallStep = 2048;
+constexpr int kSmallThreads = 1024;
+
+__global__ __launch_bounds__(kSmallThreads) void small_step_kernel(
+    int64_t n, StepInfo *__restrict__ info, const double *__restrict__ t,
+    const double *__restrict__ dt, const double *__restrict__ x, const double *__restrict__ v,
+    const double *__restrict__ a, const double *__restrict__ k, double *__restrict__ xp,
+    double *__restrict__ vp, const double *__restrict__ mass, JRec *__restrict__ jrec, int rep,
+    int32_t *__restrict__ active, int count_steps) {
+    constexpr int NW = kSmallThreads / 64;
+    __shared__ double wmin[NW];
+    __shared__ int wcnt[NW];
+    __shared__ double s_tn;
+    __shared__ int s_done;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    double mn = INFINITY;
+    for (int64_t i = tid; i < n; i += kSmallThreads) mn = fmin(mn, t[i] + dt[i]);
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) mn = fmin(mn, __shfl_xor(mn, o, 64));
+    if (lane == 0) wmin[wave] = mn;
+    __syncthreads();
+    if (tid == 0) {
+        double tn = wmin[0];
+        for (int w = 1; w < NW; ++w) tn = fmin(tn, wmin[w]);
+        const int done = !(tn <= info->t_end);
+        info->t_next = tn;
+        info->done = done;
+        if (done) info->n_i = 0;
+        s_tn = tn;
+        s_done = done;
+    }
+    __syncthreads();
+    if (s_done) return;
+    const double tn = s_tn;
+    // the block, ascending
+    int64_t base = 0;
+    for (int64_t p = 0; p < n; p += kSmallThreads) {
+        const int64_t i = p + tid;
+        const bool f = i < n && t[i] + dt[i] == tn;
+        const unsigned long long bal = __ballot(f);
+        if (lane == 0) wcnt[wave] = __popcll(bal);
+        __syncthreads();
+        int woff = 0, tot = 0;
+        for (int w = 0; w < NW; ++w) {
+            woff += (w < wave) ? wcnt[w] : 0;
+            tot += wcnt[w];
+        }
+        if (f) active[base + woff + __popcll(bal & ((1ull << lane) - 1ull))] = (int32_t)i;
+        base += tot;
+        __syncthreads();
+    }
+    // every particle predicted to t_next
+    for (int64_t i = tid; i < n; i += kSmallThreads) {
+        double px[3], pv[3];
+        predict_one(tn - t[i], x, v, a, k, i, n, px, pv);
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            xp[c * n + i] = px[c];
+            vp[c * n + i] = pv[c];
+        }
+        if (jrec) store_rec(rep, jrec + i, px[0], px[1], px[2], pv[0], pv[1], pv[2], mass[i]);
+    }
+    if (tid == 0) {
+        info->n_i = base;
+        if (count_steps) {
+            info->steps += 1;
+            info->interactions += base * n;
+        }
+    }
+}
+
 static int sched_grids(int64_t n, unsigned *g1, unsigned *g2) {
     *g1 = grid_for(n, 256 * 8, 1024);
     *g2 = grid_for(n, 1024, 1024);
@@ -520,11 +597,18 @@ int nbody_blockstep(nbody_ctx *ctx, const nbody_system *s, int64_t max_steps, do
     while (enq < max_steps) {
         int64_t todo = max_steps - enq < chunk ? max_steps - enq : chunk;
         for (int64_t q = 0; q < todo; ++q) {
-            NB_TRY(launch_schedule(ctx, n, s->t, s->dt, act, 1, nullptr, nullptr));
-            predict_kernel<<<gp, 256, 0, ctx->stream>>>(n, 0.0, ctx->info, s->t, s->x, s->v,
-                                                        s->a, s->k, xp, vp, s->m, jr,
-                                                        c.shape.rep);
-            NB_TRY(hip_check(ctx, hipGetLastError(), "predict_kernel"));
+            if (n <= kSmallStep) {
+                small_step_kernel<<<1, kSmallThreads, 0, ctx->stream>>>(
+                    n, ctx->info, s->t, s->dt, s->x, s->v, s->a, s->k, xp, vp, s->m, jr,
+                    c.shape.rep, act, 1);
+                NB_TRY(hip_check(ctx, hipGetLastError(), "small_step_kernel"));
+            } else {
+                NB_TRY(launch_schedule(ctx, n, s->t, s->dt, act, 1, nullptr, nullptr));
+                predict_kernel<<<gp, 256, 0, ctx->stream>>>(n, 0.0, ctx->info, s->t, s->x,
+                                                            s->v, s->a, s->k, xp, vp, s->m, jr,
+                                                            c.shape.rep);
+                NB_TRY(hip_check(ctx, hipGetLastError(), "predict_kernel"));
+            }
             NB_TRY(launch_force(ctx, c));
             correct_kernel<<<gp, 256, 0, ctx->stream>>>(
                 n, 0, ctx->info, ctx->info, act, xp, vp, an, kn, n, s->eta, s->dt_max, s->dt_min,
