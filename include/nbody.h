@@ -318,6 +318,37 @@ int nbody_correct_adjoint(nbody_ctx *ctx, int64_t n, double h, const double *x1_
                           double *a0_bar, double *k0_bar, double *a1_bar,
                           double *k1_bar);
 
+/* ---- differentiable shared-step run (an extension: the chain of the
+ * entry points above, orchestrated natively) ------------------------------
+ * nbody_shared_run: a, k = pair sums at (x0, v0) (nbody_force, all n
+ * particles); then n_steps shared steps of h, each nbody_predict to h,
+ * nbody_force at the predicted state, nbody_correct with the step held fixed
+ * (Section 2).  Outputs the final x, v, a, k (device float64[3n], distinct
+ * from x0, v0).  If ckpt is not NULL (device float64[ceil(n_steps /
+ * ckpt_every) * 12n]), the state (x, v, a, k, each 3n, in that order)
+ * before steps 0, ckpt_every, 2 ckpt_every, ... is stored there.
+ *   m: device float64[n]; flags: NBODY_ACC_FP32 or NBODY_ACC_DS.
+ * nbody_shared_run_adjoint: the gradient of a loss of the final (x, v, a, k)
+ * with respect to x0, v0 and m, from its cotangents x_bar, v_bar, a_bar,
+ * k_bar (device float64[3n]) and the checkpoints of nbody_shared_run with
+ * the same arguments: each segment is recomputed from its checkpoint, then
+ * nbody_correct_adjoint, nbody_force_adjoint (at the predicted state) and
+ * nbody_predict_adjoint run back through its steps; last, the transpose of
+ * the initial pair sums.  Outputs x0_bar, v0_bar (float64[3n]) and m_bar
+ * (float64[n]), overwritten.  Workspace (about (16 + 2 ckpt_every) * 3n
+ * doubles) is owned by the context.  Both return NBODY_E_INVAL for n < 1,
+ * h <= 0, n_steps < 0, ckpt_every < 1, eps2 < 0 or null arrays. */
+int nbody_shared_run(nbody_ctx *ctx, int64_t n, const double *m, double eps2, double h,
+                     int64_t n_steps, int64_t ckpt_every, const double *x0,
+                     const double *v0, double *x, double *v, double *a, double *k,
+                     double *ckpt, uint32_t flags);
+int nbody_shared_run_adjoint(nbody_ctx *ctx, int64_t n, const double *m, double eps2,
+                             double h, int64_t n_steps, int64_t ckpt_every,
+                             const double *x0, const double *v0, const double *ckpt,
+                             const double *x_bar, const double *v_bar,
+                             const double *a_bar, const double *k_bar, double *x0_bar,
+                             double *v0_bar, double *m_bar, uint32_t flags);
+
 /* ---- launch shape of the pair kernels (autotuning) ----------------------
  * The pair kernels are compiled in several shapes; a context keeps a table
  * of which shape to use for which active-block size.  Without entries a

@@ -84,6 +84,9 @@ SIGNATURES = {
     "nbody_ensemble_timing": (INT, [P, I32, P, P]),
     "nbody_ensemble_info": (INT, [P, ctypes.POINTER(I32), ctypes.POINTER(I32)]),
     "nbody_ensemble_plan": (INT, [P, I32, I32, P, D, P, P, P, ctypes.POINTER(I32)]),
+    "nbody_shared_run": (INT, [P, I64, P, D, D, I64, I64, P, P, P, P, P, P, P, U32]),
+    "nbody_shared_run_adjoint": (INT, [P, I64, P, D, D, I64, I64, P, P, P, P, P, P, P, P, P,
+                                       P, U32]),
     "nbody_force_adjoint": (INT, [P, I64, P, P, P, D, P, P, P, P, P, P, U32]),
     "nbody_predict_adjoint": (INT, [P, I64, D, P, P, P, P, P, P]),
     "nbody_correct_adjoint": (INT, [P, I64, D, P, P, P, P, P, P, P, P]),

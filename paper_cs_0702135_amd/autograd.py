@@ -8,17 +8,23 @@
   predictor transpose (nbody_correct_adjoint, nbody_force_adjoint,
   nbody_predict_adjoint).  Every arithmetic step, forward and backward, runs
   in the library's kernels; this module only allocates and wires tensors.
-* shared_run: the initial force plus `steps` HermiteSteps, recomputed in
-  segments of `checkpoint_every` steps during the backward pass
-  (torch.utils.checkpoint), so only segment boundaries are kept alive.
+* shared_run: the same run as one Function over the library's native chain
+  (nbody_shared_run / nbody_shared_run_adjoint): the initial force plus
+  `steps` shared steps, the state checkpointed every `checkpoint_every`
+  steps and each segment recomputed in the backward pass; no Python work
+  per step.
+* shared_run_steps: the same run composed from HermiteSteps under
+  torch.utils.checkpoint (per-step autograd nodes, e.g. for hooks).
 """
 from __future__ import annotations
 
 import torch
 from torch.utils.checkpoint import checkpoint
 
-from . import (correct, correct_adjoint, force, force_adjoint, predict,
-               predict_adjoint)
+import ctypes
+
+from . import (_mode, _ptr, _sca, _vec, context, correct, correct_adjoint, force,
+               force_adjoint, predict, predict_adjoint)
 
 
 def _zeros_if_none(g, like):
@@ -92,11 +98,60 @@ def _segment(x, v, a, k, mass, eps2, h, n_steps, mode):
     return x, v, a, k
 
 
+class SharedRun(torch.autograd.Function):
+    """(x, v, a, k) after the initial force and `steps` shared steps of h."""
+
+    @staticmethod
+    def forward(ctx, pos, vel, mass, eps2, h, steps, checkpoint_every, mode="fp32"):
+        n = mass.shape[0]
+        _vec(pos, n, "pos"), _vec(vel, n, "vel"), _sca(mass, n, "mass")
+        ck = int(checkpoint_every) if checkpoint_every else max(int(steps), 1)
+        x = torch.empty_like(pos)
+        v = torch.empty_like(vel)
+        a = torch.empty_like(pos)
+        k = torch.empty_like(pos)
+        keep = any(ctx.needs_input_grad[:3]) and steps > 0
+        ckpt = (torch.empty((((steps + ck - 1) // ck) * 12 * n,), dtype=torch.float64,
+                            device=pos.device) if keep else None)
+        c = context(pos.device)
+        c.check(c.lib.nbody_shared_run(c.bind(), n, _ptr(mass), float(eps2), float(h), int(steps),
+                                       ck, _ptr(pos), _ptr(vel), _ptr(x), _ptr(v), _ptr(a),
+                                       _ptr(k), _ptr(ckpt), _mode(mode)))
+        ctx.save_for_backward(pos, vel, mass, ckpt if keep else torch.empty(0))
+        ctx.eps2, ctx.h, ctx.steps, ctx.ck, ctx.mode = float(eps2), float(h), int(steps), ck, mode
+        return x, v, a, k
+
+    @staticmethod
+    def backward(ctx, g_x, g_v, g_a, g_k):
+        pos, vel, mass, ckpt = ctx.saved_tensors
+        gx = _zeros_if_none(g_x, pos)
+        gv = _zeros_if_none(g_v, pos)
+        ga = _zeros_if_none(g_a, pos)
+        gk = _zeros_if_none(g_k, pos)
+        xb = torch.empty_like(pos)
+        vb = torch.empty_like(vel)
+        mb = torch.empty_like(mass)
+        c = context(pos.device)
+        c.check(c.lib.nbody_shared_run_adjoint(
+            c.bind(), mass.shape[0], _ptr(mass), ctx.eps2, ctx.h, ctx.steps, ctx.ck, _ptr(pos),
+            _ptr(vel), _ptr(ckpt) if ckpt.numel() else None, _ptr(gx), _ptr(gv), _ptr(ga),
+            _ptr(gk), _ptr(xb), _ptr(vb), _ptr(mb), _mode(ctx.mode)))
+        return xb, vb, mb, None, None, None, None, None
+
+
 def shared_run(pos, vel, mass, eps2, h, steps, checkpoint_every=8, mode="fp32"):
-    """Initial force at t = 0, then `steps` shared Hermite steps of h.
+    """Initial force at t = 0, then `steps` shared Hermite steps of h, in the
+    library's native chain (checkpoints every `checkpoint_every` steps;
+    0 keeps one segment).
 
     Returns (x, v, a, k) at t = steps * h, differentiable in pos, vel, mass.
     """
+    return SharedRun.apply(pos, vel, mass, eps2, h, steps, checkpoint_every, mode)
+
+
+def shared_run_steps(pos, vel, mass, eps2, h, steps, checkpoint_every=8, mode="fp32"):
+    """As shared_run, composed from per-step autograd nodes (HermiteStep)
+    recomputed under torch.utils.checkpoint."""
     a, k, _ = NBodyForce.apply(pos, vel, mass, eps2, mode)
     x, v = pos, vel
     done = 0

@@ -75,6 +75,8 @@ struct nbody_ctx {
     size_t work_bytes = 0;
     void *adj = nullptr;  // adjoint source records
     size_t adj_bytes = 0;
+    void *chain = nullptr;  // differentiable shared-step run workspace
+    size_t chain_bytes = 0;
     void *ens = nullptr;  // ensemble tables, team scratch, predicted state
     size_t ens_bytes = 0;
     nbody_ensemble_config ens_cfg = {2, 64, 30.0, 15.0, 0.5, 2.0e9, 247.0, 0.35};

@@ -150,7 +150,8 @@ int nbody_destroy(nbody_ctx *ctx) {
     if (!ctx) return NBODY_OK;
     (void)hipSetDevice(ctx->device);
     (void)hipStreamSynchronize(ctx->stream);
-    void *bufs[] = {ctx->jrec, ctx->part, ctx->work, ctx->bs, ctx->adj, ctx->ens, ctx->info};
+    void *bufs[] = {ctx->jrec, ctx->part, ctx->work, ctx->bs, ctx->adj, ctx->chain, ctx->ens,
+                    ctx->info};
     for (void *b : bufs)
         if (b) (void)hipFree(b);
     if (ctx->info_host) (void)hipHostFree(ctx->info_host);

@@ -129,3 +129,31 @@ def test_full_run_gradient_vs_stored_finite_differences(orc):
     say("grad16k: %d coordinates, median rel err %.2e, max %.2e" % (rel.size, np.median(rel),
                                                                    rel.max()))
     assert np.median(rel) <= 1e-4 and rel.max() <= 1e-3
+
+
+@pytest.mark.parametrize("mode", ["fp32", "ds"])
+def test_native_chain_matches_per_step_autograd(mode):
+    # the native chain runs the same entry points as the per-step autograd
+    # composition: identical forward state, gradients equal up to the order
+    # in which the mass cotangents of the steps are added
+    need_gpu()
+    import torch
+    from paper_cs_0702135_amd.autograd import shared_run, shared_run_steps
+    n, h, steps = 600, 1.0 / 256, 11
+    pos, vel, m = plummer(n, 69)
+    eps2 = 1e-4
+    rng = np.random.default_rng(70)
+    wx, wv, wa = (dev(rng.normal(size=(3, n))) for _ in range(3))
+    res = []
+    for fn in (shared_run, shared_run_steps):
+        P = dev(pos).requires_grad_(True)
+        V = dev(vel).requires_grad_(True)
+        M = dev(m).requires_grad_(True)
+        x, v, a, k = fn(P, V, M, eps2, h, steps, checkpoint_every=4, mode=mode)
+        loss = (wx * x).sum() + (wv * v).sum() + (wa * a).sum()
+        loss.backward()
+        torch.cuda.synchronize()
+        res.append((host(x.detach()), host(P.grad), host(V.grad), host(M.grad)))
+    np.testing.assert_array_equal(res[0][0], res[1][0])
+    for got, ref in zip(res[0][1:], res[1][1:]):
+        np.testing.assert_allclose(got, ref, rtol=1e-12, atol=1e-12 * np.abs(ref).max())
