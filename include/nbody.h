@@ -25,7 +25,8 @@
  *   - Every entry returns NBODY_OK (0) or a negative status; no C++
  *     exception crosses the ABI.  nbody_last_error() gives the text of the
  *     last failure on that context.  Errors found by kernels (a time step
- *     below dt_min, a non-finite value) are latched in a device status word
+ *     below dt_min, a non-finite value, an active index out of range) are
+ *     latched in a device status word
  *     and reported by the next synchronising call (nbody_sync_status,
  *     nbody_blockstep, nbody_ensemble_run).
  *   - Results are deterministic for a fixed device and configuration: no
@@ -46,7 +47,7 @@ extern "C" {
 #define NBODY_E_INVAL (-1)     /* bad argument, detected on the host       */
 #define NBODY_E_DEVICE (-2)    /* HIP runtime error                         */
 #define NBODY_E_RANGE (-3)     /* a time step fell below dt_min             */
-#define NBODY_E_NONFINITE (-4) /* a non-finite force or step criterion      */
+#define NBODY_E_NONFINITE (-4) /* a non-finite state, force or step norm    */
 #define NBODY_E_NOMEM (-5)     /* device allocation failed                  */
 
 /* ---- flags for the force and adjoint entries ------------------------- */

@@ -46,8 +46,10 @@ def candidates(n_i: int, n_j: int, forms=(0,)):
         for it in (1, 2, 4):
             if n_i <= 64 and it > 1:
                 continue
-            for w in (1, 2, 4):
-                for tg in (8192, 32768, 65536, 131072):
+            for w in (1, 2, 4, 8):
+                if it == 4 and w == 8:  # not compiled (registers)
+                    continue
+                for tg in (8192, 32768, 65536, 131072, 262144):
                     out.append(ForceShape(rep, it, w, 128, 64, tg))
     return out
 

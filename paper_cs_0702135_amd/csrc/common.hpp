@@ -77,7 +77,7 @@ struct nbody_ctx {
     size_t adj_bytes = 0;
     void *chain = nullptr;  // differentiable shared-step run workspace
     size_t chain_bytes = 0;
-    void *ens = nullptr;  // ensemble tables, team scratch, predicted state
+    void *ens = nullptr;  // ensemble tables and team scratch
     size_t ens_bytes = 0;
     nbody_ensemble_config ens_cfg = {2, 64, 30.0, 15.0, 0.5, 2.0e9, 247.0, 0.35};
     int ens_last_grid = 0;

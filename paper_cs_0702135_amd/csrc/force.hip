@@ -8,16 +8,18 @@
 //     no VGPRs for j data in the inner loop;
 //   * each lane keeps IT i-particles;
 //   * r = x_j - x_i and w = v_j - v_i are formed to float64 accuracy (see the
-//     record forms in common.hpp) and then the pair arithmetic is float32
+//     record forms in records.hpp) and then the pair arithmetic is float32
 //     with the VALU reciprocal square root;
 //   * a wave sums `tile` consecutive j in float32, then folds the tile sum
 //     into its running sum: a float32 add (NBODY_ACC_FP32) or an exact
 //     TwoSum into a float-float pair (NBODY_ACC_DS);
 //   * the W waves of a workgroup share the same i-particles and split their
 //     j range; their sums are combined in float64 through LDS in wave order;
-//   * when the active block is too small to fill the GPU, the j range is
-//     also split across S workgroups; their float64 partial sums are added
-//     in split order by a second kernel.
+//   * the j range is also split across S workgroups when the active block
+//     is too small to fill the GPU, and into chunks of a few MB at any size
+//     so that the groups resident on an XCD share them in its L2; the
+//     float64 partial sums are added in split order by a second kernel;
+//   * workgroups take their items XCD by XCD (xcd_item in pairs.hpp).
 // The self pair is skipped by index: tiles whose j range can contain one of
 // the wave's own indices take a masked path.
 #include <algorithm>
