@@ -536,6 +536,24 @@ def main():
             "sample": "FP64 oracle pair sums for %d seeded i-particles against all %d j "
                       "(%.2e interactions, %.1f s)" % (n_s, n, n_s * (n - 1.0), dt_cpu),
         }
+        # the same oracle on one host core, over a proportionally smaller
+        # sample (about a third of the multi-core sample's wall time)
+        n_1 = int(max(64, n_s / max(1, cores) / 3))
+        one = sample[:n_1]
+        oracle.set_num_threads(1)
+        try:
+            ta = time.perf_counter()
+            oracle.force(pos, vel, m, eps2, active=one)
+            dt_1 = time.perf_counter() - ta
+        finally:
+            oracle.set_num_threads(cores)
+        out["cpu_baseline_one_core"] = {
+            "value": n_1 * (n - 1) / dt_1,
+            "unit": "interactions/s",
+            "cores": 1,
+            "kind": "oracle",
+            "sample": "the first %d of the same i-particles (%.1f s)" % (n_1, dt_1),
+        }
     print(json.dumps(out), flush=True)
 
 

@@ -22,6 +22,7 @@ struct StepInfo {
     int64_t done;         // 1 once the next block would pass t_end
     int64_t steps;        // block steps executed since the last reset
     int64_t interactions; // sum of n_i * n over those steps
+    double rest_min;      // min of t + dt outside the current block (driver)
     int32_t status;       // latched NBODY_E_* bits (see status_bits)
     uint32_t ticket0;     // arrival counters of the last-block reductions
     uint32_t ticket1;

@@ -98,6 +98,48 @@ __device__ __forceinline__ bool is_active(const double *t, const double *dt, int
     return t[i] + dt[i] == tn;
 }
 
+// Exclusive scan, in block order, of the per-block counts of a grid of at
+// most 1024 blocks of 256 threads, in place; returns the total.  Run by all
+// threads of the one (last) block: each thread scans 4 consecutive counts,
+// then a block scan of the 256 thread totals.
+__device__ int64_t block_order_scan(int64_t *counts) {
+    __shared__ int64_t tsum[256];
+    int64_t cb[4], run = 0;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const unsigned b = threadIdx.x * 4 + q;
+        cb[q] = b < gridDim.x ? __builtin_nontemporal_load(&counts[b]) : 0;
+        run += cb[q];
+    }
+    tsum[threadIdx.x] = run;
+    __syncthreads();
+    for (int o = 1; o < 256; o <<= 1) {
+        const int64_t v = (int)threadIdx.x >= o ? tsum[threadIdx.x - o] : 0;
+        __syncthreads();
+        tsum[threadIdx.x] += v;
+        __syncthreads();
+    }
+    int64_t off = tsum[threadIdx.x] - run;  // exclusive prefix of this thread
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const unsigned b = threadIdx.x * 4 + q;
+        if (b < gridDim.x) counts[b] = off;
+        off += cb[q];
+    }
+    return tsum[255];
+}
+
+// Minimum over the 256 threads of a block (every thread gets it).
+__device__ double block_min(double m) {
+    __shared__ double wm[4];
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) m = fmin(m, __shfl_xor(m, o, 64));
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0) wm[threadIdx.x >> 6] = m;
+    __syncthreads();
+    return fmin(fmin(wm[0], wm[1]), fmin(wm[2], wm[3]));
+}
+
 __global__ __launch_bounds__(256) void sched_count_kernel(
     int64_t n, const double *__restrict__ t, const double *__restrict__ dt,
     int64_t *__restrict__ counts, StepInfo *__restrict__ info, int count_steps,
@@ -133,34 +175,8 @@ __global__ __launch_bounds__(256) void sched_count_kernel(
     __syncthreads();
     if (!last) return;
     __threadfence();
-    // exclusive scan of the per-block counts (gridDim.x <= 1024), in block
-    // order: each thread scans 4 consecutive counts, then a block scan of the
-    // 256 thread totals
-    __shared__ int64_t tsum[256];
-    int64_t cb[4], run = 0;
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-        const unsigned b = threadIdx.x * 4 + q;
-        cb[q] = b < gridDim.x ? __builtin_nontemporal_load(&counts[b]) : 0;
-        run += cb[q];
-    }
-    tsum[threadIdx.x] = run;
-    __syncthreads();
-    for (int o = 1; o < 256; o <<= 1) {
-        const int64_t v = (int)threadIdx.x >= o ? tsum[threadIdx.x - o] : 0;
-        __syncthreads();
-        tsum[threadIdx.x] += v;
-        __syncthreads();
-    }
-    int64_t off = tsum[threadIdx.x] - run;  // exclusive prefix of this thread
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-        const unsigned b = threadIdx.x * 4 + q;
-        if (b < gridDim.x) counts[b] = off;
-        off += cb[q];
-    }
+    const int64_t total = block_order_scan(counts);
     if (threadIdx.x == 255) {
-        const int64_t total = tsum[255];
         info->n_i = total;
         if (count_steps) {
             info->steps += 1;
@@ -172,19 +188,12 @@ __global__ __launch_bounds__(256) void sched_count_kernel(
     }
 }
 
-__global__ __launch_bounds__(256) void sched_compact_kernel(int64_t n,
-                                                            const double *__restrict__ t,
-                                                            const double *__restrict__ dt,
-                                                            const int64_t *__restrict__ offsets,
-                                                            const StepInfo *__restrict__ info,
-                                                            int32_t *__restrict__ active) {
+// Writes the indices i in [lo, hi) with t + dt == tn to active[base...] in
+// ascending order (all threads of a block of 256).
+__device__ void compact_chunk(int64_t lo, int64_t hi, int64_t base, double tn,
+                              const double *__restrict__ t, const double *__restrict__ dt,
+                              int32_t *__restrict__ active) {
     __shared__ int wsum[4];
-    if (info->done) return;
-    const double tn = info->t_next;
-    const int64_t chunk = (n + gridDim.x - 1) / gridDim.x;
-    const int64_t lo = blockIdx.x * chunk;
-    const int64_t hi = lo + chunk < n ? lo + chunk : n;
-    int64_t base = offsets[blockIdx.x];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     for (int64_t p = lo; p < hi; p += blockDim.x) {
         const int64_t i = p + threadIdx.x;
@@ -202,6 +211,143 @@ __global__ __launch_bounds__(256) void sched_compact_kernel(int64_t n,
         base += tot;
         __syncthreads();
     }
+}
+
+__global__ __launch_bounds__(256) void sched_compact_kernel(int64_t n,
+                                                            const double *__restrict__ t,
+                                                            const double *__restrict__ dt,
+                                                            const int64_t *__restrict__ offsets,
+                                                            const StepInfo *__restrict__ info,
+                                                            int32_t *__restrict__ active) {
+    if (info->done) return;
+    const double tn = info->t_next;
+    const int64_t chunk = (n + gridDim.x - 1) / gridDim.x;
+    const int64_t lo = blockIdx.x * chunk;
+    const int64_t hi = lo + chunk < n ? lo + chunk : n;
+    compact_chunk(lo, hi, offsets[blockIdx.x], tn, t, dt, active);
+}
+
+// Block step of the driver for n > kSmallStep, without grid-wide fences:
+// each kernel leaves per-block partial results that the next kernel folds
+// (every block of it redundantly where all need the value), so the launch
+// boundaries order the passes.
+//   step_scan_kernel    t_next (see below); per chunk of particles the
+//                       number in the block (t + dt == t_next), the minimum
+//                       of t + dt over the others, and the prediction of
+//                       every particle to t_next (state and j records);
+//   step_compact_kernel each chunk's offset = the counts of the chunks
+//                       before it, then the chunk's block indices in
+//                       ascending order; chunk 0 also writes n_i and folds
+//                       the minima outside the block into rest_min;
+//   pair sums, corrector (correct_kernel with `mins`: per corrector block
+//                       the minimum of the new t + dt of its particles).
+// The next step's t_next is the minimum of rest_min and the corrector's
+// minima; at the first step of a call it comes from sched_min_kernel.  The
+// block, its order, the predicted values and t_next are those of the
+// separate sched_min / sched_count / sched_compact / predict passes.
+__global__ __launch_bounds__(256) void step_scan_kernel(
+    int64_t n, StepInfo *__restrict__ info, int fold, const double *__restrict__ cmin,
+    int ncmin, const double *__restrict__ t, const double *__restrict__ dt,
+    const double *__restrict__ x, const double *__restrict__ v, const double *__restrict__ a,
+    const double *__restrict__ k, double *__restrict__ xp, double *__restrict__ vp,
+    const double *__restrict__ mass, JRec *__restrict__ jrec, int rep,
+    int64_t *__restrict__ counts, double *__restrict__ rmin) {
+    __shared__ int64_t red[256];
+    if (info->done) return;
+    double tn;
+    if (fold) {
+        double m = INFINITY;
+        for (int b = threadIdx.x; b < ncmin; b += blockDim.x) m = fmin(m, cmin[b]);
+        tn = fmin(block_min(m), info->rest_min);
+        const bool done = !(tn <= info->t_end);
+        if (blockIdx.x == 0 && threadIdx.x == 0) {
+            info->t_next = tn;
+            if (done) {
+                info->n_i = 0;
+                info->done = 1;
+            }
+        }
+        if (done) return;
+    } else {
+        tn = info->t_next;
+    }
+    const int64_t chunk = (n + gridDim.x - 1) / gridDim.x;
+    const int64_t lo = blockIdx.x * chunk;
+    const int64_t hi = lo + chunk < n ? lo + chunk : n;
+    int64_t c = 0;
+    double m = INFINITY;
+    for (int64_t i = lo + threadIdx.x; i < hi; i += blockDim.x) {
+        const double ti = t[i];
+        const double e = ti + dt[i];
+        if (e == tn)
+            ++c;
+        else
+            m = fmin(m, e);
+        double px[3], pv[3];
+        predict_one(tn - ti, x, v, a, k, i, n, px, pv);
+#pragma unroll
+        for (int q = 0; q < 3; ++q) {
+            xp[q * n + i] = px[q];
+            vp[q * n + i] = pv[q];
+        }
+        store_rec(rep, jrec + i, px[0], px[1], px[2], pv[0], pv[1], pv[2], mass[i]);
+    }
+    m = block_min(m);
+    red[threadIdx.x] = c;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+        if ((int)threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        counts[blockIdx.x] = red[0];
+        rmin[blockIdx.x] = m;
+    }
+}
+
+// Sum over the 256 threads of a block (every thread gets it).
+__device__ int64_t block_sum(int64_t c) {
+    __shared__ int64_t ws[4];
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) c += __shfl_xor(c, o, 64);
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0) ws[threadIdx.x >> 6] = c;
+    __syncthreads();
+    return (ws[0] + ws[1]) + (ws[2] + ws[3]);
+}
+
+__global__ __launch_bounds__(256) void step_compact_kernel(int64_t n, StepInfo *__restrict__ info,
+                                                           const double *__restrict__ t,
+                                                           const double *__restrict__ dt,
+                                                           const int64_t *__restrict__ counts,
+                                                           const double *__restrict__ rmin,
+                                                           int32_t *__restrict__ active) {
+    if (info->done) return;
+    const double tn = info->t_next;
+    const int64_t chunk = (n + gridDim.x - 1) / gridDim.x;
+    const int64_t lo = blockIdx.x * chunk;
+    const int64_t hi = lo + chunk < n ? lo + chunk : n;
+    // chunk 0 (offset 0) totals the counts and folds the minima; the
+    // others sum the counts of the chunks before them
+    const unsigned upto = blockIdx.x == 0 ? gridDim.x : blockIdx.x;
+    int64_t c = 0;
+    double m = INFINITY;
+    for (unsigned b = threadIdx.x; b < upto; b += blockDim.x) {
+        c += counts[b];
+        if (blockIdx.x == 0) m = fmin(m, rmin[b]);
+    }
+    c = block_sum(c);
+    if (blockIdx.x == 0) {
+        m = block_min(m);
+        if (threadIdx.x == 0) {
+            info->n_i = c;
+            info->rest_min = m;
+            info->steps += 1;
+            info->interactions += c * n;
+        }
+        c = 0;
+    }
+    compact_chunk(lo, hi, c, tn, t, dt, active);
 }
 
 // Small systems (n <= kSmallStep): the whole scheduling part of a block step
@@ -322,10 +468,17 @@ __global__ void correct_kernel(int64_t n, int64_t n_i_arg, const StepInfo *__res
                                double eta, double dt_max, double dt_min, int fixed_dt,
                                double *__restrict__ t, double *__restrict__ dtv,
                                double *__restrict__ x, double *__restrict__ v,
-                               double *__restrict__ a, double *__restrict__ k) {
+                               double *__restrict__ a, double *__restrict__ k,
+                               double *__restrict__ mins) {
 #pragma clang fp contract(off)
+    // with `mins` (the block-step driver, blocks of 256 threads): also the
+    // minimum of the new t + dt of the block's particles, per corrector
+    // block (infinity for blocks without one), for the next step's t_next;
+    // nothing once the run is done (no block was scheduled)
+    if (mins && cinfo->done) return;
     const int64_t n_i = cinfo ? cinfo->n_i : n_i_arg;
     const int64_t sn = stride_new > 0 ? stride_new : n_i;
+    double m = INFINITY;
     for (int64_t s = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; s < n_i;
          s += (int64_t)gridDim.x * blockDim.x) {
         int64_t i = active ? (int64_t)active[s] : s;
@@ -342,7 +495,11 @@ __global__ void correct_kernel(int64_t n, int64_t n_i_arg, const StepInfo *__res
         const int32_t st = correct_one(i, n, xp, vp, a1v, k1v, eta, dt_max, dt_min, fixed_dt, t,
                                        dtv, x, v, a, k);
         if (st) latch(sinfo, st);
+        if (mins) m = fmin(m, t[i] + dtv[i]);
     }
+    if (!mins) return;
+    m = block_min(m);
+    if (threadIdx.x == 0) mins[blockIdx.x] = m;
 }
 
 // ------------------------------------------------------------ initial steps
@@ -476,7 +633,7 @@ int nbody_correct(nbody_ctx *ctx, int64_t n, int64_t n_i, const int32_t *active_
     NB_TRY(activate(ctx));
     correct_kernel<<<grid_for(n_i, 256, 16 * ctx->cus), 256, 0, ctx->stream>>>(
         n, n_i, nullptr, ctx->info, active_idx, xp, vp, acc_new, jerk_new, n_i, eta, dt_max,
-        dt_min, fixed_dt, t, dt, x, v, a, k);
+        dt_min, fixed_dt, t, dt, x, v, a, k, nullptr);
     return hip_check(ctx, hipGetLastError(), "correct_kernel");
 }
 
@@ -592,27 +749,53 @@ int nbody_blockstep(nbody_ctx *ctx, const nbody_system *s, int64_t max_steps, do
     c.out_stride = n;
     c.ds = (s->flags & NBODY_ACC_DS) != 0;
 
+    // Systems of up to kSmallStep particles schedule and predict in one
+    // workgroup per step.  Larger ones take three launches besides the pair
+    // sums (step_scan_kernel, step_compact_kernel, the corrector with its
+    // per-block minima); the first t_next of the call comes from
+    // sched_min_kernel, the later ones are folded by step_scan_kernel.
+    const bool small = n <= kSmallStep;
     const unsigned gp = grid_for(n, 256, 16 * ctx->cus);
+    const unsigned gs = grid_for(n, 256, 1024);  // step_scan / step_compact chunks
+    const unsigned gc = grid_for(n, 256, 1024);  // corrector blocks (driver)
+    double *rmin = nullptr, *cmin = nullptr;
+    int64_t *counts = nullptr;
+    if (!small) {
+        NB_TRY(ensure(ctx, &ctx->work, &ctx->work_bytes, 4096 * sizeof(double)));
+        double *partial = (double *)ctx->work;
+        counts = (int64_t *)ctx->work + 1024;
+        rmin = (double *)ctx->work + 2048;
+        cmin = (double *)ctx->work + 3072;
+        unsigned g1, g2;
+        sched_grids(n, &g1, &g2);
+        sched_min_kernel<<<g1, 256, 0, ctx->stream>>>(n, s->t, s->dt, partial, ctx->info);
+        NB_TRY(hip_check(ctx, hipGetLastError(), "sched_min_kernel"));
+    }
+    int fold = 0;
     int64_t enq = 0, chunk = 4;
     while (enq < max_steps) {
         int64_t todo = max_steps - enq < chunk ? max_steps - enq : chunk;
         for (int64_t q = 0; q < todo; ++q) {
-            if (n <= kSmallStep) {
+            if (small) {
                 small_step_kernel<<<1, kSmallThreads, 0, ctx->stream>>>(
                     n, ctx->info, s->t, s->dt, s->x, s->v, s->a, s->k, xp, vp, s->m, jr,
                     c.shape.rep, act, 1);
                 NB_TRY(hip_check(ctx, hipGetLastError(), "small_step_kernel"));
             } else {
-                NB_TRY(launch_schedule(ctx, n, s->t, s->dt, act, 1, nullptr, nullptr));
-                predict_kernel<<<gp, 256, 0, ctx->stream>>>(n, 0.0, ctx->info, s->t, s->x,
-                                                            s->v, s->a, s->k, xp, vp, s->m, jr,
-                                                            c.shape.rep);
-                NB_TRY(hip_check(ctx, hipGetLastError(), "predict_kernel"));
+                step_scan_kernel<<<gs, 256, 0, ctx->stream>>>(
+                    n, ctx->info, fold, cmin, (int)gc, s->t, s->dt, s->x, s->v, s->a, s->k, xp,
+                    vp, s->m, jr, c.shape.rep, counts, rmin);
+                NB_TRY(hip_check(ctx, hipGetLastError(), "step_scan_kernel"));
+                fold = 1;
+                step_compact_kernel<<<gs, 256, 0, ctx->stream>>>(n, ctx->info, s->t, s->dt,
+                                                                 counts, rmin, act);
+                NB_TRY(hip_check(ctx, hipGetLastError(), "step_compact_kernel"));
             }
             NB_TRY(launch_force(ctx, c));
-            correct_kernel<<<gp, 256, 0, ctx->stream>>>(
+            correct_kernel<<<small ? gp : gc, 256, 0, ctx->stream>>>(
                 n, 0, ctx->info, ctx->info, act, xp, vp, an, kn, n, s->eta, s->dt_max, s->dt_min,
-                (s->flags & NBODY_FIXED_DT) ? 1 : 0, s->t, s->dt, s->x, s->v, s->a, s->k);
+                (s->flags & NBODY_FIXED_DT) ? 1 : 0, s->t, s->dt, s->x, s->v, s->a, s->k,
+                small ? nullptr : cmin);
             NB_TRY(hip_check(ctx, hipGetLastError(), "correct_kernel"));
         }
         enq += todo;
