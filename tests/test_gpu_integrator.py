@@ -127,6 +127,41 @@ def test_blockstep_steps_match_oracle_from_same_state(orc):
     assert flips <= 2
 
 
+@pytest.mark.parametrize("n,fixed", [(2049, False), (3001, False), (70001, False),
+                                     (300001, False), (5000, True)])
+def test_blockstep_multi_step_calls_equal_single_step_calls(orc, n, fixed):
+    # Above 2048 particles the driver takes the block time of a step from
+    # the minimum outside the previous block and the corrected particles'
+    # new t + dt (folded per workgroup), except at the first step of a call
+    # (a full minimum).  K steps in one call must therefore equal K calls of
+    # one step bit for bit, and every block time must be the oracle's
+    # schedule of the state before the step.  Sizes with ragged chunks, the
+    # chunk cap (300001 > 1024 chunks of 256), and shared steps (every
+    # particle active: nothing outside the block).
+    need_gpu()
+    import paper_cs_0702135_amd as nb
+    pos, vel, m = plummer(n, 50 + n % 97)
+    K = 12 if n > 100000 else 30
+    args = (dev(pos), dev(vel), dev(m), 1.0 / 256 ** 2)
+    kw = dict(eta=0.02, dt_max=0.125, fixed_dt=fixed)
+    one = nb.System(*args, **kw)
+    many = nb.System(*args, **kw)
+    times = []
+    for _ in range(K):
+        t_before = host(one.t)
+        tn, act = orc.schedule(t_before, host(one.dt))
+        assert one.step(1) == 1
+        t_after = host(one.t)
+        # exactly the oracle's block moved, to the oracle's block time
+        np.testing.assert_array_equal(np.flatnonzero(t_after != t_before), act)
+        assert np.all(t_after[act] == tn)
+        times.append(tn)
+    assert many.step(K) == K
+    for q in ("t", "dt", "x", "v", "a", "k"):
+        np.testing.assert_array_equal(host(getattr(many, q)), host(getattr(one, q)), err_msg=q)
+    say("n=%d fixed=%s: %d steps to t=%.6g, multi-step call bitwise equal" % (n, fixed, K, times[-1]))
+
+
 @pytest.mark.parametrize("mode", ["fp32", "ds"])
 def test_blockstep_energy_drift(orc, mode):
     # Plummer N=1024, eps=1/256, eta=0.02, to t=1/4: relative energy drift
