@@ -119,6 +119,24 @@ def ensemble_only(args):
     print(json.dumps(out), flush=True)
 
 
+def host_cpu():
+    """The host the oracle ran on: CPU model, logical CPUs, CPUs this process may use."""
+    model = None
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        usable = len(os.sched_getaffinity(0))
+    except (AttributeError, OSError):
+        usable = None
+    return {"model": model, "logical_cpus": os.cpu_count(), "usable_cpus": usable}
+
+
 def paper_table(args):
     """The Section 4 results-table protocol on one GPU: for each N, one
     seeded Plummer realisation, eps = 1/256, eta = 0.02, dt_max = 1/8,
@@ -547,6 +565,7 @@ def main():
             dt_1 = time.perf_counter() - ta
         finally:
             oracle.set_num_threads(cores)
+        out["cpu_host"] = host_cpu()
         out["cpu_baseline_one_core"] = {
             "value": n_1 * (n - 1) / dt_1,
             "unit": "interactions/s",
