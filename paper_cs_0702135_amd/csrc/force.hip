@@ -18,7 +18,8 @@
 //   * the j range is also split across S workgroups when the active block
 //     is too small to fill the GPU, and into chunks of a few MB at any size
 //     so that the groups resident on an XCD share them in its L2; the
-//     float64 partial sums are added in split order by a second kernel;
+//     partial sums (float32 for float32 sums, float64 for compensated ones)
+//     are added in split order, in float64, by a second kernel;
 //   * workgroups take their items XCD by XCD (xcd_item in pairs.hpp).
 // The self pair is skipped by index: tiles whose j range can contain one of
 // the wave's own indices take a masked path.
@@ -332,10 +333,16 @@ __global__ __launch_bounds__(64 * W) void force_kernel(const KArgs a) {
                         a.jerk[ostride + s] = tot[t][4];
                         a.jerk[2 * ostride + s] = tot[t][5];
                         if (a.pot) a.pot[s] = tot[t][6];
-                    } else {
+                    } else if (DS) {
                         double *p = a.part + (sp * 7) * n_i + s;
 #pragma unroll
                         for (int q = 0; q < 7; ++q) p[q * n_i] = tot[t][q];
+                    } else {
+                        // float32 sums: the partial is kept to float32
+                        // precision (half the traffic of the split partials)
+                        float *p = (float *)a.part + (sp * 7) * n_i + s;
+#pragma unroll
+                        for (int q = 0; q < 7; ++q) p[q * n_i] = (float)tot[t][q];
                     }
                 }
             }
@@ -365,8 +372,13 @@ __global__ __launch_bounds__(64 * RW) void reduce_parts_kernel(const KArgs a, in
         double acc = 0.0;
         if (e < total) {
             const int64_t q = e / n_i, s = e - q * n_i;
-            const double *src = a.part + q * n_i + s;
-            for (int64_t p = p0; p < p1; ++p) acc += src[p * 7 * n_i];
+            if (a.part_f32) {
+                const float *src = (const float *)a.part + q * n_i + s;
+                for (int64_t p = p0; p < p1; ++p) acc += (double)src[p * 7 * n_i];
+            } else {
+                const double *src = a.part + q * n_i + s;
+                for (int64_t p = p0; p < p1; ++p) acc += src[p * 7 * n_i];
+            }
         }
         red[wave][lane] = acc;
         __syncthreads();
@@ -499,9 +511,12 @@ int launch_force(nbody_ctx *ctx, const ForceCall &c) {
     a.target_groups = sh.target_groups;
     a.max_splits = kMaxSplits;
     a.accumulate = 0;
+    a.part_f32 = c.ds ? 0 : 1;
+    const int64_t part_elem = c.ds ? (int64_t)sizeof(double) : (int64_t)sizeof(float);
 
-    // Partial-sum scratch: S * 7 * n_i doubles.  When S > 1 the number of
-    // i-blocks is below target_groups, so S * n_i <= 2 * target_groups * 64 * it.
+    // Partial-sum scratch: S * 7 * n_i values (float64 for compensated sums,
+    // float32 for float32 sums).  When S > 1 the number of i-blocks is below
+    // target_groups, so S * n_i <= 2 * target_groups * 64 * it.
     const int64_t bi = 64 * sh.it;
     int64_t items, need_part;
     if (dev_count) {
@@ -523,14 +538,14 @@ int launch_force(nbody_ctx *ctx, const ForceCall &c) {
         // S * n_i <= S * nb * bi <= items * bi, and <= 2 * target_groups * bi
         // (S > 1 only while nb < target_groups)
         const int64_t part_rows = std::min<int64_t>(2 * tg, items) * bi;
-        need_part = part_rows * 7 * (int64_t)sizeof(double);
+        need_part = part_rows * 7 * part_elem;
         if (items > (1 << 24)) items = 1 << 24;
     } else {
         int64_t S = choose_splits(c.n_i, c.n_j, sh.it, sh.waves, sh.min_j_wave,
                                   sh.target_groups, kMaxSplits);
         int64_t nb = (c.n_i + bi - 1) / bi;
         items = nb * S;
-        need_part = S > 1 ? S * 7 * c.n_i * (int64_t)sizeof(double) : 0;
+        need_part = S > 1 ? S * 7 * c.n_i * part_elem : 0;
         if (items > (1 << 24)) items = 1 << 24;
     }
     if (need_part > 0) {

@@ -32,6 +32,7 @@ struct KArgs {
     int32_t target_groups;
     int32_t max_splits;
     int32_t accumulate;  // 1: add into acc/jerk/pot instead of overwriting
+    int32_t part_f32;    // 1: split partials stored as float32 (float32 sums)
 };
 
 // Number of workgroups that share one i-block's j range.
@@ -81,8 +82,9 @@ __device__ __forceinline__ int wave_max(int v) {
     return v;
 }
 
-// Adds the S float64 partial sums [S][7][n_i] of the 7 outputs in split
-// order and writes acc (q < 3), jerk (q < 6) and pot (q = 6).
+// Adds the S partial sums [S][7][n_i] of the 7 outputs (float64, or
+// float32 with KArgs::part_f32) in split order, in float64, and writes acc
+// (q < 3), jerk (q < 6) and pot (q = 6).
 int launch_reduce_parts(nbody_ctx *ctx, const KArgs &a, int it, int waves, int64_t n_i_max);
 
 }  // namespace nb
