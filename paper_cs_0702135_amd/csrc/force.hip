@@ -451,17 +451,18 @@ static force_fn pick_kernel(const ForceShape &s, bool ds) {
 // and FMA latencies) and two waves.  The target of 128 groups per CU (32768
 // in all) makes the j splits small enough for the groups resident on an
 // XCD to share their j chunk in L2.  Up to n_j = 8192 a wave may take as
-// few as 16 j: a lone wave walking a long chain of scalar j loads is
-// latency-bound, so small systems split j over more workgroups (13-28 %
-// faster block steps at N = 256 ... 8192); beyond, finer splits cost more
-// in partial sums than they hide (64 j per wave).
+// few as n_j / 256 j (2 ... 16): a lone wave walking a long chain of scalar
+// j loads is latency-bound, so small systems split j over more workgroups
+// (13-28 % faster block steps at N = 256 ... 8192 with 16 j, another 6-19 %
+// at N = 256 ... 2048 with 2-8 j); beyond, finer splits cost more in
+// partial sums than they hide (64 j per wave).
 static ForceShape default_shape(const nbody_ctx *ctx, int64_t n_i, int64_t n_j) {
     ForceShape s;
     s.rep = REP_F64;
     s.it = n_i >= 256 ? 2 : 1;
     s.waves = n_i >= 1024 ? 2 : 4;
     s.tile = 128;
-    s.min_j_wave = n_j <= 8192 ? 16 : 64;
+    s.min_j_wave = n_j <= 8192 ? (int)std::min<int64_t>(16, std::max<int64_t>(2, n_j / 256)) : 64;
     s.target_groups = 128 * ctx->cus;
     return s;
 }

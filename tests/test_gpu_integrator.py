@@ -127,17 +127,19 @@ def test_blockstep_steps_match_oracle_from_same_state(orc):
     assert flips <= 2
 
 
-@pytest.mark.parametrize("n,fixed", [(2049, False), (3001, False), (70001, False),
-                                     (300001, False), (5000, True)])
+@pytest.mark.parametrize("n,fixed", [(100, False), (1000, False), (2048, False),
+                                     (2049, False), (3001, False), (70001, False),
+                                     (300001, False), (64, True), (5000, True)])
 def test_blockstep_multi_step_calls_equal_single_step_calls(orc, n, fixed):
-    # Above 2048 particles the driver takes the block time of a step from
-    # the minimum outside the previous block and the corrected particles'
-    # new t + dt (folded per workgroup), except at the first step of a call
-    # (a full minimum).  K steps in one call must therefore equal K calls of
-    # one step bit for bit, and every block time must be the oracle's
-    # schedule of the state before the step.  Sizes with ragged chunks, the
-    # chunk cap (300001 > 1024 chunks of 256), and shared steps (every
-    # particle active: nothing outside the block).
+    # Within one call the driver carries work across steps: above 2048
+    # particles the block time of a step is folded from the minimum outside
+    # the previous block and the corrected particles' new t + dt (except at
+    # the first step of a call: a full minimum).  K steps in one call must
+    # therefore equal K calls of one step bit for bit, and every block time
+    # must be the oracle's schedule of the state before the step.  Sizes on
+    # both sides of 2048 (up to 2048 one workgroup schedules every step),
+    # with ragged chunks, the chunk cap (300001 > 1024 chunks of 256), and
+    # shared steps (every particle active).
     need_gpu()
     import paper_cs_0702135_amd as nb
     pos, vel, m = plummer(n, 50 + n % 97)
