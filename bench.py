@@ -228,8 +228,8 @@ def paper_table(args):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=3)
-    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--mode", choices=("fp32", "ds"), default="fp32")
     ap.add_argument("--n", type=int, default=1 << 20)
     ap.add_argument("--cpu-seconds", type=float, default=12.0,
@@ -298,20 +298,26 @@ def main():
     for _ in range(args.warmup):
         assert sysg.step(1) == 1
     torch.cuda.synchronize()
-    nb.profile(1)
+    # HIP events around every pair-kernel launch, read back after each step
+    # (each step synchronises anyway): average and median per launch
+    per_launch, force_ms, reduce_ms, launches = [], 0.0, 0.0, 0
     t0 = time.perf_counter()
     for k in range(args.steps):
+        nb.profile(1)
         assert sysg.step(1) == 1
-        log("bench: step %d done" % (k + 1))
+        f_ms, r_ms, nl = nb.profile(0)
+        force_ms, reduce_ms, launches = force_ms + f_ms, reduce_ms + r_ms, launches + nl
+        per_launch.append(f_ms / max(1, nl))
+        log("bench: step %d done (pair kernel %.1f ms)" % (k + 1, per_launch[-1]))
     torch.cuda.synchronize()
     t1 = time.perf_counter()
-    force_ms, reduce_ms, launches = nb.profile(0)
     wall = t1 - t0
     inter_step = float(n) * (n - 1)
     value = args.steps * inter_step / wall
     ms_step = wall / args.steps * 1e3
 
     k_ms = force_ms / max(1, launches)
+    k_med = float(np.median(per_launch))
     achieved = FLOPS_PER_INTERACTION * inter_step / (k_ms * 1e-3) / 1e12
     roofline = {
         "bound": "alu",
@@ -322,6 +328,7 @@ def main():
         "frac": round(achieved / FP32_PEAK_TFLOPS, 4),
         "traffic": measured_traffic(),
         "kernel_ms": round(k_ms, 3),
+        "kernel_ms_median": round(k_med, 3),
         "flops_per_interaction": FLOPS_PER_INTERACTION,
         "reduce_ms": round(reduce_ms / max(1, launches), 3),
     }
