@@ -260,7 +260,7 @@ def main():
         return
 
     if args.gpus != 1:
-        print("bench.py measures one GPU: this build has no multi-GPU path "
+        print("bench.py measures one GPU: there is no multi-GPU path "
               "(the j-parallel sharding is a design note only); run with --gpus 1.",
               file=sys.stderr)
         sys.exit(2)
