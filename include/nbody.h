@@ -51,11 +51,20 @@ extern "C" {
 #define NBODY_E_NOMEM (-5)     /* device allocation failed                  */
 
 /* ---- flags for the force and adjoint entries ------------------------- */
-/* Relative positions and velocities are always formed in float64 and then
- * rounded to float32; the pair arithmetic is float32 (rsqrt on the VALU);
- * the flag selects how the float32 pair terms are accumulated. */
-#define NBODY_ACC_FP32 0u /* two-level float32 sums (tile sums folded in fp32) */
-#define NBODY_ACC_DS 1u   /* tile sums folded by TwoSum into a float-float pair */
+/* Relative positions and velocities are always formed in float64.  The flag
+ * selects the pair arithmetic and its accumulation:
+ *   NBODY_ACC_FP32  relative coordinates rounded to float32, float32 pair
+ *                   terms (rsqrt on the VALU) summed in float32 over tiles
+ *                   of consecutive j, the tile sums added in float64;
+ *   NBODY_ACC_DS    the compensated (accurate) mode.  nbody_force,
+ *                   nbody_init / nbody_blockstep and nbody_shared_run
+ *                   evaluate the pair terms in float64 (s^(-1/2) from the
+ *                   float32 estimate refined by a float64 Newton step) with
+ *                   float64 sums; the ensemble and the adjoint keep float32
+ *                   pair terms and fold their tile sums by TwoSum into
+ *                   float-float sums. */
+#define NBODY_ACC_FP32 0u
+#define NBODY_ACC_DS 1u
 /* nbody_system.flags only: every particle keeps the step it has (dt_max after
  * nbody_init), i.e. shared steps in which every block step advances all
  * particles; the step criterion is not evaluated. */

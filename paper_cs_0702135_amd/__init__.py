@@ -13,6 +13,7 @@ listing (softened acceleration, jerk and potential).
 """
 from __future__ import annotations
 
+import atexit
 import ctypes
 import math
 import threading
@@ -65,16 +66,39 @@ class Context:
     def sync_status(self):
         self.check(self.lib.nbody_sync_status(self.bind()))
 
+    def close(self):
+        """Synchronise the context's stream and free its device memory."""
+        h = getattr(self, "h", None)
+        if h:
+            self.h = None
+            self.lib.nbody_destroy(h)
+
     def __del__(self):
+        # contexts still open at interpreter exit were closed by
+        # _close_all (atexit) while the HIP runtime was fully alive
         try:
-            if getattr(self, "h", None):
-                self.lib.nbody_destroy(self.h)
+            self.close()
         except Exception:
             pass
 
 
 _ctx = {}
 _ctx_lock = threading.Lock()
+_atexit_registered = False
+
+
+def _close_all():
+    """Destroy every context (registered with atexit at the first context:
+    it runs before torch's and the HIP runtime's own teardown, so no library
+    call is made during interpreter or runtime finalisation)."""
+    with _ctx_lock:
+        ctxs = list(_ctx.values())
+        _ctx.clear()
+    for c in ctxs:
+        try:
+            c.close()
+        except Exception:
+            pass
 
 
 def context(device=None) -> Context:
@@ -83,8 +107,12 @@ def context(device=None) -> Context:
     dev = torch.cuda.current_device() if device is None else torch.device(device).index
     if dev is None:
         dev = torch.cuda.current_device()
+    global _atexit_registered
     with _ctx_lock:
         if dev not in _ctx:
+            if not _atexit_registered:
+                atexit.register(_close_all)
+                _atexit_registered = True
             _ctx[dev] = Context(dev)
         return _ctx[dev]
 

@@ -108,6 +108,11 @@ void prof_push(nbody_ctx *ctx, hipEvent_t a, hipEvent_t b, int kind);
 void prof_resolve(nbody_ctx *ctx);
 
 ForceShape pick_shape(const nbody_ctx *ctx, int64_t n_i, int64_t n_j);
+// Pair-arithmetic mode (ACC_* in pairs.hpp) of the NBODY_ACC_* flags, and
+// the shape a mode runs in: float64 pair terms need float64 records and take
+// at most two i-particles per lane.
+int acc_mode(uint32_t flags);
+ForceShape shape_for(ForceShape s, int acc);
 
 // Pair-sum launch used by nbody_force and the block-step driver.
 //   n_i_dev != nullptr: the block size is read on the device (at most
@@ -125,7 +130,7 @@ struct ForceCall {
     double eps2 = 0;
     double *acc = nullptr, *jerk = nullptr, *pot = nullptr;
     int64_t out_stride = 0;
-    bool ds = false;
+    int mode = 0;  // accumulation, ACC_* (pairs.hpp)
 };
 int launch_force(nbody_ctx *ctx, const ForceCall &c);
 int launch_pack(nbody_ctx *ctx, int rep, int64_t n, const double *pos,

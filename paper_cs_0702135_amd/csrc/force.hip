@@ -8,18 +8,20 @@
 //     no VGPRs for j data in the inner loop;
 //   * each lane keeps IT i-particles;
 //   * r = x_j - x_i and w = v_j - v_i are formed to float64 accuracy (see the
-//     record forms in records.hpp) and then the pair arithmetic is float32
-//     with the VALU reciprocal square root;
-//   * a wave sums `tile` consecutive j in float32, then folds the tile sum
-//     into its running sum: a float32 add (NBODY_ACC_FP32) or an exact
-//     TwoSum into a float-float pair (NBODY_ACC_DS);
+//     record forms in records.hpp);
+//   * float32 mode: the pair arithmetic is float32 with the VALU reciprocal
+//     square root; a wave sums `tile` consecutive j in float32 and adds each
+//     tile sum to a per-lane float64 total in LDS;
+//   * compensated mode: the pair arithmetic is float64 (gfx950 issues
+//     float64 FMAs at the rate of unpacked float32 ones), s^(-1/2) from the
+//     float32 estimate refined by one float64 Newton step, float64 sums;
 //   * the W waves of a workgroup share the same i-particles and split their
 //     j range; their sums are combined in float64 through LDS in wave order;
 //   * the j range is also split across S workgroups when the active block
 //     is too small to fill the GPU, and into chunks of a few MB at any size
 //     so that the groups resident on an XCD share them in its L2; the
-//     partial sums (float32 for float32 sums, float64 for compensated ones)
-//     are added in split order, in float64, by a second kernel;
+//     partial sums (float32 in the float32 mode, float64 otherwise) are
+//     added in split order, in float64, by a second kernel;
 //   * workgroups take their items XCD by XCD (xcd_item in pairs.hpp).
 // The self pair is skipped by index: tiles whose j range can contain one of
 // the wave's own indices take a masked path.
@@ -152,10 +154,11 @@ struct Form<REP_F64V> {
     }
 };
 
-template <int REP, int IT, int W, bool DS>
+template <int REP, int IT, int W, int ACC>
 __global__ __launch_bounds__(64 * W) void force_kernel(const KArgs a) {
     typedef Form<REP> F;
     typedef typename F::Rec Rec;
+    static_assert(ACC != ACC_F64 || REP == REP_F64, "float64 pair terms need float64 records");
     const int64_t n_i = a.n_i_dev ? *a.n_i_dev : a.n_i;
     if (n_i <= 0) return;
     const int n_j = a.n_j;
@@ -167,13 +170,17 @@ __global__ __launch_bounds__(64 * W) void force_kernel(const KArgs a) {
     const int64_t items = nb * S;
     const int64_t jchunk = (n_j + S - 1) / S;
     const float eps2 = a.eps2;
+    const double eps2d = a.eps2d;
     const int tile = a.tile;
     // Constant address space: the records are read-only during the kernel
     // and their addresses are wave-uniform, so every field is fetched with a
     // scalar load into SGPRs.
     const CONSTP(JRec) J = (CONSTP(JRec))a.jrec;
 
-    __shared__ double red[W > 1 ? W - 1 : 1][7 * IT][64];
+    // Per-wave float64 totals of each lane's sums: the running totals of
+    // the float32 tile sums (ACC_F32), and the slices the waves of the
+    // group combine in wave order at the end of an item.
+    __shared__ double red[W][7 * IT][64];
 
     for (int64_t q = blockIdx.x; q < items; q += gridDim.x) {
         const int64_t item = xcd_item(q, items);
@@ -207,109 +214,150 @@ __global__ __launch_bounds__(64 * W) void force_kernel(const KArgs a) {
         lo_idx = __builtin_amdgcn_readfirstlane(wave_min(lo_idx));
         hi_idx = __builtin_amdgcn_readfirstlane(wave_max(hi_idx));
 
-        // running sums: hi parts (and lo parts for DS); the potential is
-        // accumulated as +sum m/r and negated when stored
-        float sax[IT], say[IT], saz[IT], sjx[IT], sjy[IT], sjz[IT], sph[IT];
-        float lax[IT], lay[IT], laz[IT], ljx[IT], ljy[IT], ljz[IT], lph[IT];
+        // Running sums: ACC_F32 adds each float32 tile sum to a float64
+        // total kept in LDS; ACC_F64 keeps float64 sums in registers.  The
+        // potential is accumulated as +sum m/r and negated when stored.
+        double sd[IT][7];
 #pragma unroll
-        for (int t = 0; t < IT; ++t) {
-            sax[t] = say[t] = saz[t] = sjx[t] = sjy[t] = sjz[t] = sph[t] = 0.0f;
-            lax[t] = lay[t] = laz[t] = ljx[t] = ljy[t] = ljz[t] = lph[t] = 0.0f;
-        }
+        for (int t = 0; t < IT; ++t)
+#pragma unroll
+            for (int k = 0; k < 7; ++k) {
+                sd[t][k] = 0.0;
+                if (ACC == ACC_F32) red[wave][t * 7 + k][lane] = 0.0;
+            }
 
         for (int jt = jb; jt < je; jt += tile) {
             const int jend = min(je, jt + tile);
-            float iax[IT], iay[IT], iaz[IT], ijx[IT], ijy[IT], ijz[IT], iph[IT];
+            const bool masked = jt <= hi_idx && jend > lo_idx;
+            if constexpr (ACC == ACC_F64) {
+                // float64 relative coordinates and pair terms; s^(-1/2)
+                // from the float32 hardware estimate, refined by one
+                // Newton step in float64 (relative error ~1e-14)
+                auto body64 = [&](const RecF64 &r, const int j, const bool mask)
+                    __attribute__((always_inline)) {
 #pragma unroll
-            for (int t = 0; t < IT; ++t)
-                iax[t] = iay[t] = iaz[t] = ijx[t] = ijy[t] = ijz[t] = iph[t] = 0.0f;
-
-            auto body = [&](const Rec &r, const int j, const bool mask)
-                __attribute__((always_inline)) {
-#pragma unroll
-                for (int t = 0; t < IT; ++t) {
-                    float dx, dy, dz, du, dv, dw;
-                    F::rel(r, own[t], dx, dy, dz, du, dv, dw);
-                    float s2 = fmaf(dz, dz, fmaf(dy, dy, fmaf(dx, dx, eps2)));
-                    float mj = r.m;
-                    if (mask) {
-                        const bool self = (j == idx[t]);
-                        s2 = self ? 1.0f : s2;
-                        mj = self ? 0.0f : mj;
+                    for (int t = 0; t < IT; ++t) {
+                        const double dx = r.x - own[t].x, dy = r.y - own[t].y,
+                                     dz = r.z - own[t].z;
+                        const double du = r.u - own[t].u, dv = r.v - own[t].v,
+                                     dw = r.w - own[t].w;
+                        double s2 = fma(dz, dz, fma(dy, dy, fma(dx, dx, eps2d)));
+                        double mj = r.md;
+                        if (mask) {
+                            const bool self = (j == idx[t]);
+                            s2 = self ? 1.0 : s2;
+                            mj = self ? 0.0 : mj;
+                        }
+                        const double rv = fma(dz, dw, fma(dy, dv, dx * du));
+                        const double y0 = (double)__builtin_amdgcn_rsqf((float)s2);
+                        const double e = fma(-(s2 * y0), y0, 1.0);
+                        const double y = fma(0.5 * y0, e, y0);
+                        const double y2 = y * y;
+                        const double mr3 = (mj * y) * y2;
+                        const double w3 = (rv * y2) * -3.0;
+                        sd[t][0] = fma(mr3, dx, sd[t][0]);
+                        sd[t][1] = fma(mr3, dy, sd[t][1]);
+                        sd[t][2] = fma(mr3, dz, sd[t][2]);
+                        sd[t][3] = fma(mr3, fma(w3, dx, du), sd[t][3]);
+                        sd[t][4] = fma(mr3, fma(w3, dy, dv), sd[t][4]);
+                        sd[t][5] = fma(mr3, fma(w3, dz, dw), sd[t][5]);
+                        sd[t][6] = fma(mj, y, sd[t][6]);
                     }
-                    const float rv = fmaf(dz, dw, fmaf(dy, dv, dx * du));
-                    const float rinv = __builtin_amdgcn_rsqf(s2);
-                    const float rinv2 = rinv * rinv;
-                    const float mr1 = mj * rinv;
-                    const float mr3 = mr1 * rinv2;
-                    const float w3 = (rv * rinv2) * -3.0f;
-                    iax[t] = fmaf(mr3, dx, iax[t]);
-                    iay[t] = fmaf(mr3, dy, iay[t]);
-                    iaz[t] = fmaf(mr3, dz, iaz[t]);
-                    ijx[t] = fmaf(mr3, fmaf(w3, dx, du), ijx[t]);
-                    ijy[t] = fmaf(mr3, fmaf(w3, dy, dv), ijy[t]);
-                    ijz[t] = fmaf(mr3, fmaf(w3, dz, dw), ijz[t]);
-                    iph[t] = fmaf(mj, rinv, iph[t]);
-                }
-            };
-
-            if (jt <= hi_idx && jend > lo_idx) {
-                for (int j = jt; j < jend; ++j) {
-                    const Rec r = F::load(J, j);
-                    body(r, j, true);
+                };
+                CONSTP(RecF64) R = (CONSTP(RecF64))J;
+                auto load64 = [&](int j) __attribute__((always_inline)) {
+                    RecF64 r;
+                    r.x = R[j].x; r.y = R[j].y; r.z = R[j].z; r.md = R[j].md;
+                    r.u = R[j].u; r.v = R[j].v; r.w = R[j].w;
+                    return r;
+                };
+                if (masked) {
+                    for (int j = jt; j < jend; ++j) body64(load64(j), j, true);
+                } else {
+                    RecF64 cur = load64(jt);
+#pragma unroll 2
+                    for (int j = jt; j < jend; ++j) {
+                        const RecF64 nxt = load64(min(j + 1, jend - 1));
+                        body64(cur, j, false);
+                        cur = nxt;
+                    }
                 }
             } else {
-                // software pipelined: the next record's scalar loads are in
-                // flight while the current one is used
-                Rec cur = F::load(J, jt);
-#pragma unroll 4
-                for (int j = jt; j < jend; ++j) {
-                    const Rec nxt = F::load(J, min(j + 1, jend - 1));
-                    body(cur, j, false);
-                    cur = nxt;
-                }
-            }
-
-#pragma unroll
-            for (int t = 0; t < IT; ++t) {
-                if (DS) {
-                    two_sum_acc(sax[t], lax[t], iax[t]);
-                    two_sum_acc(say[t], lay[t], iay[t]);
-                    two_sum_acc(saz[t], laz[t], iaz[t]);
-                    two_sum_acc(sjx[t], ljx[t], ijx[t]);
-                    two_sum_acc(sjy[t], ljy[t], ijy[t]);
-                    two_sum_acc(sjz[t], ljz[t], ijz[t]);
-                    two_sum_acc(sph[t], lph[t], iph[t]);
-                } else {
-                    sax[t] += iax[t];
-                    say[t] += iay[t];
-                    saz[t] += iaz[t];
-                    sjx[t] += ijx[t];
-                    sjy[t] += ijy[t];
-                    sjz[t] += ijz[t];
-                    sph[t] += iph[t];
-                }
-            }
-        }
-
-        // per-wave totals in float64 (hi + lo is exact in float64)
-        double tot[IT][7];
-#pragma unroll
-        for (int t = 0; t < IT; ++t) {
-            tot[t][0] = (double)sax[t] + (double)lax[t];
-            tot[t][1] = (double)say[t] + (double)lay[t];
-            tot[t][2] = (double)saz[t] + (double)laz[t];
-            tot[t][3] = (double)sjx[t] + (double)ljx[t];
-            tot[t][4] = (double)sjy[t] + (double)ljy[t];
-            tot[t][5] = (double)sjz[t] + (double)ljz[t];
-            tot[t][6] = -((double)sph[t] + (double)lph[t]);
-        }
-        if (W > 1) {
-            if (wave > 0) {
+                float ts[IT][7];
 #pragma unroll
                 for (int t = 0; t < IT; ++t)
 #pragma unroll
-                    for (int q = 0; q < 7; ++q) red[wave - 1][t * 7 + q][lane] = tot[t][q];
+                    for (int k = 0; k < 7; ++k) ts[t][k] = 0.0f;
+
+                auto body = [&](const Rec &r, const int j, const bool mask)
+                    __attribute__((always_inline)) {
+#pragma unroll
+                    for (int t = 0; t < IT; ++t) {
+                        float dx, dy, dz, du, dv, dw;
+                        F::rel(r, own[t], dx, dy, dz, du, dv, dw);
+                        float s2 = fmaf(dz, dz, fmaf(dy, dy, fmaf(dx, dx, eps2)));
+                        float mj = r.m;
+                        if (mask) {
+                            const bool self = (j == idx[t]);
+                            s2 = self ? 1.0f : s2;
+                            mj = self ? 0.0f : mj;
+                        }
+                        const float rv = fmaf(dz, dw, fmaf(dy, dv, dx * du));
+                        const float rinv = __builtin_amdgcn_rsqf(s2);
+                        const float rinv2 = rinv * rinv;
+                        const float mr1 = mj * rinv;
+                        const float mr3 = mr1 * rinv2;
+                        const float w3 = (rv * rinv2) * -3.0f;
+                        ts[t][0] = fmaf(mr3, dx, ts[t][0]);
+                        ts[t][1] = fmaf(mr3, dy, ts[t][1]);
+                        ts[t][2] = fmaf(mr3, dz, ts[t][2]);
+                        ts[t][3] = fmaf(mr3, fmaf(w3, dx, du), ts[t][3]);
+                        ts[t][4] = fmaf(mr3, fmaf(w3, dy, dv), ts[t][4]);
+                        ts[t][5] = fmaf(mr3, fmaf(w3, dz, dw), ts[t][5]);
+                        ts[t][6] = fmaf(mj, rinv, ts[t][6]);
+                    }
+                };
+
+                if (masked) {
+                    for (int j = jt; j < jend; ++j) {
+                        const Rec r = F::load(J, j);
+                        body(r, j, true);
+                    }
+                } else {
+                    // software pipelined: the next record's scalar loads are
+                    // in flight while the current one is used
+                    Rec cur = F::load(J, jt);
+#pragma unroll 4
+                    for (int j = jt; j < jend; ++j) {
+                        const Rec nxt = F::load(J, min(j + 1, jend - 1));
+                        body(cur, j, false);
+                        cur = nxt;
+                    }
+                }
+
+                // (the barrier keeps the LDS totals from being loaded
+                // before the j loop, which would hold them in registers)
+                __asm__ volatile("" ::: "memory");
+#pragma unroll
+                for (int t = 0; t < IT; ++t)
+#pragma unroll
+                    for (int k = 0; k < 7; ++k) red[wave][t * 7 + k][lane] += (double)ts[t][k];
+            }
+        }
+
+        // per-wave totals in float64
+        double tot[IT][7];
+#pragma unroll
+        for (int t = 0; t < IT; ++t)
+#pragma unroll
+            for (int k = 0; k < 7; ++k)
+                tot[t][k] = ACC == ACC_F32 ? red[wave][t * 7 + k][lane] : sd[t][k];
+        if (W > 1) {
+            if (ACC != ACC_F32 && wave > 0) {
+#pragma unroll
+                for (int t = 0; t < IT; ++t)
+#pragma unroll
+                    for (int k = 0; k < 7; ++k) red[wave][t * 7 + k][lane] = tot[t][k];
             }
             __syncthreads();
             if (wave == 0) {
@@ -317,12 +365,13 @@ __global__ __launch_bounds__(64 * W) void force_kernel(const KArgs a) {
 #pragma unroll
                     for (int t = 0; t < IT; ++t)
 #pragma unroll
-                        for (int q = 0; q < 7; ++q) tot[t][q] += red[w - 1][t * 7 + q][lane];
+                        for (int k = 0; k < 7; ++k) tot[t][k] += red[w][t * 7 + k][lane];
             }
         }
         if (wave == 0) {
 #pragma unroll
             for (int t = 0; t < IT; ++t) {
+                tot[t][6] = -tot[t][6];
                 if (slot[t] < n_i) {
                     const int64_t s = slot[t];
                     if (S == 1) {
@@ -333,16 +382,16 @@ __global__ __launch_bounds__(64 * W) void force_kernel(const KArgs a) {
                         a.jerk[ostride + s] = tot[t][4];
                         a.jerk[2 * ostride + s] = tot[t][5];
                         if (a.pot) a.pot[s] = tot[t][6];
-                    } else if (DS) {
+                    } else if (!a.part_f32) {
                         double *p = a.part + (sp * 7) * n_i + s;
 #pragma unroll
-                        for (int q = 0; q < 7; ++q) p[q * n_i] = tot[t][q];
+                        for (int k = 0; k < 7; ++k) p[k * n_i] = tot[t][k];
                     } else {
                         // float32 sums: the partial is kept to float32
                         // precision (half the traffic of the split partials)
                         float *p = (float *)a.part + (sp * 7) * n_i + s;
 #pragma unroll
-                        for (int q = 0; q < 7; ++q) p[q * n_i] = (float)tot[t][q];
+                        for (int k = 0; k < 7; ++k) p[k * n_i] = (float)tot[t][k];
                     }
                 }
             }
@@ -405,44 +454,59 @@ int launch_reduce_parts(nbody_ctx *ctx, const KArgs &a, int it, int waves, int64
 
 typedef void (*force_fn)(const KArgs);
 
-template <int REP, int IT, bool DS>
+template <int REP, int IT, int ACC>
 static force_fn pick_w(int w) {
     switch (w) {
-        case 1: return force_kernel<REP, IT, 1, DS>;
-        case 2: return force_kernel<REP, IT, 2, DS>;
-        case 4: return force_kernel<REP, IT, 4, DS>;
-        case 8: return force_kernel<REP, IT, 8, DS>;
+        case 1: return force_kernel<REP, IT, 1, ACC>;
+        case 2: return force_kernel<REP, IT, 2, ACC>;
+        case 4: return force_kernel<REP, IT, 4, ACC>;
+        case 8: return force_kernel<REP, IT, 8, ACC>;
         default: return nullptr;
     }
 }
 
-template <int REP, bool DS>
+template <int REP, int ACC>
 static force_fn pick_w4(int w) {
     switch (w) {
-        case 1: return force_kernel<REP, 4, 1, DS>;
-        case 2: return force_kernel<REP, 4, 2, DS>;
-        case 4: return force_kernel<REP, 4, 4, DS>;
+        case 1: return force_kernel<REP, 4, 1, ACC>;
+        case 2: return force_kernel<REP, 4, 2, ACC>;
+        case 4: return force_kernel<REP, 4, 4, ACC>;
         default: return nullptr;
     }
 }
 
-template <int REP>
-static force_fn pick_it(int it, int w, bool ds) {
-    if (it == 1) return ds ? pick_w<REP, 1, true>(w) : pick_w<REP, 1, false>(w);
-    if (it == 2) return ds ? pick_w<REP, 2, true>(w) : pick_w<REP, 2, false>(w);
-    if (it == 4) return ds ? pick_w4<REP, true>(w) : pick_w4<REP, false>(w);
+template <int REP, int ACC>
+static force_fn pick_it(int it, int w) {
+    if (it == 1) return pick_w<REP, 1, ACC>(w);
+    if (it == 2) return pick_w<REP, 2, ACC>(w);
+    if (it == 4) return pick_w4<REP, ACC>(w);
     return nullptr;
 }
 
-static force_fn pick_kernel(const ForceShape &s, bool ds) {
+static force_fn pick_kernel(const ForceShape &s, int acc) {
+    if (acc == ACC_F64) {
+        if (s.rep != REP_F64) return nullptr;
+        if (s.it == 1) return pick_w<REP_F64, 1, ACC_F64>(s.waves);
+        if (s.it == 2) return pick_w<REP_F64, 2, ACC_F64>(s.waves);
+        return nullptr;
+    }
     switch (s.rep) {
-        case REP_F64: return pick_it<REP_F64>(s.it, s.waves, ds);
-        case REP_FF: return pick_it<REP_FF>(s.it, s.waves, ds);
-        case REP_F64V: return pick_it<REP_F64V>(s.it, s.waves, ds);
+        case REP_F64: return pick_it<REP_F64, ACC_F32>(s.it, s.waves);
+        case REP_FF: return pick_it<REP_FF, ACC_F32>(s.it, s.waves);
+        case REP_F64V: return pick_it<REP_F64V, ACC_F32>(s.it, s.waves);
         default: return nullptr;
     }
 }
 
+int acc_mode(uint32_t flags) { return (flags & NBODY_ACC_DS) ? ACC_F64 : ACC_F32; }
+
+ForceShape shape_for(ForceShape s, int acc) {
+    if (acc == ACC_F64) {
+        s.rep = REP_F64;
+        if (s.it > 2) s.it = 2;
+    }
+    return s;
+}
 
 // Built-in shape for an active block of about n_i particles against n_j,
 // following what the autotuner and the block-step runs find on the MI355X:
@@ -499,10 +563,10 @@ int launch_force(nbody_ctx *ctx, const ForceCall &c) {
     const int64_t n_i_max = dev_count ? c.n_i_cap : c.n_i;
     if (n_i_max <= 0) return NBODY_OK;
     const ForceShape &sh = c.shape;
-    force_fn fn = pick_kernel(sh, c.ds);
+    force_fn fn = pick_kernel(sh, c.mode);
     if (!fn)
-        return fail(ctx, NBODY_E_INVAL, "no pair kernel for rep=%d it=%d waves=%d", sh.rep, sh.it,
-                    sh.waves);
+        return fail(ctx, NBODY_E_INVAL, "no pair kernel for rep=%d it=%d waves=%d acc=%d", sh.rep,
+                    sh.it, sh.waves, c.mode);
 
     KArgs a;
     a.jrec = c.jrec;
@@ -519,13 +583,14 @@ int launch_force(nbody_ctx *ctx, const ForceCall &c) {
     a.out_stride = c.out_stride;
     a.n_j = (int32_t)c.n_j;
     a.eps2 = (float)c.eps2;
+    a.eps2d = c.eps2;
     a.tile = sh.tile;
     a.min_j_wave = sh.min_j_wave;
     a.target_groups = sh.target_groups;
     a.max_splits = kMaxSplits;
     a.accumulate = 0;
-    a.part_f32 = c.ds ? 0 : 1;
-    const int64_t part_elem = c.ds ? (int64_t)sizeof(double) : (int64_t)sizeof(float);
+    a.part_f32 = c.mode == ACC_F32 ? 1 : 0;
+    const int64_t part_elem = a.part_f32 ? (int64_t)sizeof(float) : (int64_t)sizeof(double);
 
     // Partial-sum scratch: S * 7 * n_i values (float64 for compensated sums,
     // float32 for float32 sums).  When S > 1 the number of i-blocks is below
@@ -538,7 +603,7 @@ int launch_force(nbody_ctx *ctx, const ForceCall &c) {
         // keeps the concurrently running groups on one or two j chunks).
         const int64_t nb_max = (n_i_max + bi - 1) / bi;
         int64_t smax = c.n_j / ((int64_t)sh.waves * sh.min_j_wave);
-        if (smax > kMaxSplits) smax = kMaxSplits;
+        if (smax > a.max_splits) smax = a.max_splits;
         if (smax < 1) smax = 1;
         const int64_t tg = sh.target_groups;
         int64_t a1 = (tg + smax - 1) / smax;  // below this nb, S = smax
@@ -555,24 +620,25 @@ int launch_force(nbody_ctx *ctx, const ForceCall &c) {
         if (items > (1 << 24)) items = 1 << 24;
     } else {
         int64_t S = choose_splits(c.n_i, c.n_j, sh.it, sh.waves, sh.min_j_wave,
-                                  sh.target_groups, kMaxSplits);
+                                  sh.target_groups, a.max_splits);
         int64_t nb = (c.n_i + bi - 1) / bi;
         items = nb * S;
         need_part = S > 1 ? S * 7 * c.n_i * part_elem : 0;
         if (items > (1 << 24)) items = 1 << 24;
     }
+    const bool prof = ctx->prof.on;
     if (need_part > 0) {
         NB_TRY(ensure(ctx, &ctx->part, &ctx->part_bytes, (size_t)need_part));
         a.part = (double *)ctx->part;
     }
-    hipEvent_t e0 = ctx->prof.on ? prof_mark(ctx) : nullptr;
+    hipEvent_t e0 = prof ? prof_mark(ctx) : nullptr;
     hipLaunchKernelGGL(fn, dim3((unsigned)items), dim3(64 * sh.waves), 0, ctx->stream, a);
     NB_TRY(hip_check(ctx, hipGetLastError(), "force_kernel"));
-    if (ctx->prof.on) prof_push(ctx, e0, prof_mark(ctx), 0);
+    if (prof) prof_push(ctx, e0, prof_mark(ctx), 0);
     if (need_part > 0) {
-        hipEvent_t r0 = ctx->prof.on ? prof_mark(ctx) : nullptr;
+        hipEvent_t r0 = prof ? prof_mark(ctx) : nullptr;
         NB_TRY(launch_reduce_parts(ctx, a, sh.it, sh.waves, n_i_max));
-        if (ctx->prof.on) prof_push(ctx, r0, prof_mark(ctx), 1);
+        if (prof) prof_push(ctx, r0, prof_mark(ctx), 1);
     }
     return NBODY_OK;
 }
@@ -597,7 +663,8 @@ extern "C" int nbody_force(nbody_ctx *ctx, const int32_t *active_idx, int64_t n_
     if (n_i == 0) return NBODY_OK;
     NB_TRY(activate(ctx));
     ForceCall c;
-    c.shape = pick_shape(ctx, n_i, n_j);
+    c.mode = acc_mode(flags);
+    c.shape = shape_for(pick_shape(ctx, n_i, n_j), c.mode);
     NB_TRY(ensure(ctx, &ctx->jrec, &ctx->jrec_bytes, (size_t)n_j * sizeof(JRec)));
     NB_TRY(launch_pack(ctx, c.shape.rep, n_j, pos, vel, mass, (JRec *)ctx->jrec));
     c.jrec = (const JRec *)ctx->jrec;
@@ -611,6 +678,5 @@ extern "C" int nbody_force(nbody_ctx *ctx, const int32_t *active_idx, int64_t n_
     c.jerk = jerk;
     c.pot = pot;
     c.out_stride = n_i;
-    c.ds = (flags & NBODY_ACC_DS) != 0;
     return launch_force(ctx, c);
 }

@@ -688,7 +688,8 @@ int nbody_init(nbody_ctx *ctx, const nbody_system *s, double t0) {
     NB_TRY(hip_check(ctx, hipGetLastError(), "fill_kernel"));
     NB_TRY(ensure(ctx, &ctx->jrec, &ctx->jrec_bytes, (size_t)n * sizeof(JRec)));
     ForceCall c;
-    c.shape = pick_shape(ctx, n, n);
+    c.mode = acc_mode(s->flags);
+    c.shape = shape_for(pick_shape(ctx, n, n), c.mode);
     NB_TRY(launch_pack(ctx, c.shape.rep, n, s->x, s->v, s->m, (JRec *)ctx->jrec));
     c.jrec = (const JRec *)ctx->jrec;
     c.n_j = n;
@@ -699,7 +700,6 @@ int nbody_init(nbody_ctx *ctx, const nbody_system *s, double t0) {
     c.acc = s->a;
     c.jerk = s->k;
     c.out_stride = n;
-    c.ds = (s->flags & NBODY_ACC_DS) != 0;
     NB_TRY(launch_force(ctx, c));
     if (s->flags & NBODY_FIXED_DT) {
         fill_kernel<<<grid_for(n, 256, 4 * ctx->cus), 256, 0, ctx->stream>>>(n, s->dt_max, s->dt);
@@ -734,7 +734,8 @@ int nbody_blockstep(nbody_ctx *ctx, const nbody_system *s, int64_t max_steps, do
     NB_TRY(hip_check(ctx, hipGetLastError(), "set_info"));
 
     ForceCall c;
-    c.shape = dynamic_shape(ctx, n);
+    c.mode = acc_mode(s->flags);
+    c.shape = shape_for(dynamic_shape(ctx, n), c.mode);
     c.jrec = jr;
     c.n_j = n;
     c.pos = xp;
@@ -747,7 +748,6 @@ int nbody_blockstep(nbody_ctx *ctx, const nbody_system *s, int64_t max_steps, do
     c.jerk = kn;
     c.pot = nullptr;
     c.out_stride = n;
-    c.ds = (s->flags & NBODY_ACC_DS) != 0;
 
     // Systems of up to kSmallStep particles schedule and predict in one
     // workgroup per step.  Larger ones take three launches besides the pair

@@ -10,6 +10,15 @@ namespace nb {
 #define CONSTP(T) const __attribute__((address_space(4))) T *
 
 constexpr int kMaxSplits = 1024;  // largest j split across workgroups
+
+// Arithmetic and accumulation of the pair terms:
+//   ACC_F32  (NBODY_ACC_FP32) float32 pair terms summed in float32 over a
+//            tile of consecutive j; each tile sum is added to a float64
+//            total, so no float32 sum spans more than one tile whatever the
+//            launch shape;
+//   ACC_F64  (NBODY_ACC_DS) float64 pair terms and float64 sums (float64
+//            records only).
+enum { ACC_F32 = 0, ACC_F64 = 1 };
 constexpr int RW = 8;             // waves per group of the split reduction
 
 struct KArgs {
@@ -27,6 +36,7 @@ struct KArgs {
     int64_t out_stride;  // <= 0: use n_i
     int32_t n_j;
     float eps2;
+    double eps2d;
     int32_t tile;
     int32_t min_j_wave;
     int32_t target_groups;

@@ -10,7 +10,8 @@ namespace nb {
 // Packed j-particle records read by the pair kernels through the scalar
 // data path: one 64-byte record per particle (whole-record scalar loads), so
 // the record lands in SGPRs that every lane of a wave reads as operands.
-// The mass is float32 in every form (it only enters float32 products).  The
+// The mass is float32 in every form (it enters the float32 products); the
+// float64 form also carries it in float64 for float64 pair terms.  The
 // form of the relative coordinates r = x_j - x_i, w = v_j - v_i is a launch
 // choice (ForceShape::rep):
 //   REP_F64  positions and velocities in float64; r and w are float64
@@ -27,7 +28,7 @@ struct __attribute__((aligned(64))) RecF64 {
     double x, y, z;
     float m, pad0;
     double u, v, w;
-    double pad1;
+    double md;  // the mass in float64
 };
 struct __attribute__((aligned(64))) RecFF {
     float xh, yh, zh, m;
@@ -84,7 +85,7 @@ __device__ inline void store_rec(int rep, JRec *out, double x, double y, double 
         r.u = u;
         r.v = v;
         r.w = w;
-        r.pad1 = 0.0;
+        r.md = m;
         *out = r;
     }
 }

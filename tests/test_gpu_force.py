@@ -1,13 +1,17 @@
 """GPU parity of the pair sums (nbody_force) against the FP64 oracle.
 
 Same seeded inputs on both sides; the oracle is plain float64 over j in
-ascending order.  Tolerances (the gate for float32 pair arithmetic with
-float64-formed relative coordinates): per-particle relative error of the
-acceleration vector at the 99th percentile <= 1e-5 with float32 tile sums
-and, with the compensated (float-float) sums, <= 1e-6 -- at these sizes
-both modes sit on the float32 pair-arithmetic floor (~2e-7), where the
-compensation has nothing left to win; potential likewise;
-jerk is reported and only sanity-bounded (its sum cancels strongly).
+ascending order.  Gates on the per-particle relative error of the vector
+(acceleration, jerk) or value (potential), over every particle evaluated:
+
+* float32 mode (float64-formed relative coordinates, float32 pair terms,
+  float32 tile sums added in float64): acceleration p99 <= 1e-6 and
+  max <= 1e-5 (the 1e-5 target holds for every particle; at these sizes a
+  few close pairs carry most of a particle's force, so the float32 pair
+  term itself, ~1e-7 per pair, sets the floor); potential p99 <= 1e-6;
+  jerk p99 <= 1e-5 and max <= 1e-4 (its sum cancels more strongly);
+* compensated mode (float64 pair terms and sums): acceleration, jerk and
+  potential p99 <= 1e-12 and max <= 1e-10.
 """
 import math
 
@@ -19,8 +23,9 @@ from workloads.plummer import plummer, random_active_set
 
 pytestmark = pytest.mark.gpu
 
-# float32 pair arithmetic floors both modes near 1e-7 per pair at these sizes
-TOL = {"fp32": 1e-5, "ds": 1e-6}
+# mode: (acc p99, acc max, pot p99, jerk p99, jerk max)
+GATES = {"fp32": (1e-6, 1e-5, 1e-6, 1e-5, 1e-4),
+         "ds": (1e-12, 1e-10, 1e-12, 1e-12, 1e-10)}
 
 
 def _run(pos, vel, m, eps2, active=None, mode="fp32"):
@@ -38,12 +43,15 @@ def _check(orc, pos, vel, m, eps2, active=None, mode="fp32", label=""):
     ej = rel_vec_err(got[1], ref[1])
     ep = np.abs(got[2] - ref[2]) / np.abs(ref[2])
     say("%s mode=%s n_i=%d: acc p50 %.2e p99 %.2e max %.2e | pot p99 %.2e | jerk p50 %.2e p99 %.2e"
-        % (label, mode, ea.size, np.median(ea), np.percentile(ea, 99), ea.max(),
-           np.percentile(ep, 99), np.median(ej), np.percentile(ej, 99)))
+        " max %.2e" % (label, mode, ea.size, np.median(ea), np.percentile(ea, 99), ea.max(),
+                       np.percentile(ep, 99), np.median(ej), np.percentile(ej, 99), ej.max()))
     assert np.isfinite(got[0]).all() and np.isfinite(got[1]).all() and np.isfinite(got[2]).all()
-    assert np.percentile(ea, 99) <= TOL[mode]
-    assert np.percentile(ep, 99) <= TOL[mode]
-    assert np.median(ej) <= 100 * TOL[mode]
+    a99, amax, p99, j99, jmax = GATES[mode]
+    assert np.percentile(ea, 99) <= a99
+    assert ea.max() <= amax
+    assert np.percentile(ep, 99) <= p99
+    assert np.percentile(ej, 99) <= j99
+    assert ej.max() <= jmax
     return ea, ej, ep
 
 
@@ -84,26 +92,29 @@ def test_circular_binary_without_softening(mode):
     pos = np.array([[-0.7 * d, 0.3 * d], [0.0, 0.0], [0.0, 0.0]])
     vel = np.array([[0.0, 0.0], [-0.7 * d * w, 0.3 * d * w], [0.0, 0.0]])
     acc, jerk, pot = _run(pos, vel, m, 0.0, mode=mode)
-    np.testing.assert_allclose(acc, -w * w * pos, rtol=1e-6, atol=1e-7)
-    np.testing.assert_allclose(jerk, -w * w * vel, rtol=1e-6, atol=1e-7)
-    np.testing.assert_allclose(pot, [-0.7 / d, -0.3 / d], rtol=1e-6)
+    tol = 1e-6 if mode == "fp32" else 1e-13
+    np.testing.assert_allclose(acc, -w * w * pos, rtol=tol, atol=tol / 10)
+    np.testing.assert_allclose(jerk, -w * w * vel, rtol=tol, atol=tol / 10)
+    np.testing.assert_allclose(pot, [-0.7 / d, -0.3 / d], rtol=tol)
 
 
-def test_newton_third_law_on_gpu():
-    # float32 pair terms are not exactly antisymmetric, but sum m a is
-    # small compared with sum m |a|
+@pytest.mark.parametrize("mode,tol", [("fp32", 1e-6), ("ds", 1e-13)])
+def test_newton_third_law_on_gpu(mode, tol):
+    # the pair terms are not exactly antisymmetric in floating point, but
+    # sum m a is small compared with sum m |a|
     need_gpu()
     pos, vel, m = plummer(4096, 12)
-    acc, jerk, _ = _run(pos, vel, m, 1e-6, mode="ds")
-    assert np.abs((m * acc).sum(1)).max() < 1e-6 * (m * np.abs(acc)).sum()
+    acc, jerk, _ = _run(pos, vel, m, 1e-6, mode=mode)
+    assert np.abs((m * acc).sum(1)).max() < tol * (m * np.abs(acc)).sum()
 
 
-def test_deterministic_rerun():
+@pytest.mark.parametrize("mode", ["fp32", "ds"])
+def test_deterministic_rerun(mode):
     need_gpu()
     pos, vel, m = plummer(3000, 13)
     act = random_active_set(3000, 100, 14)
-    r1 = _run(pos, vel, m, 1e-5, act, "fp32")
-    r2 = _run(pos, vel, m, 1e-5, act, "fp32")
+    r1 = _run(pos, vel, m, 1e-5, act, mode)
+    r2 = _run(pos, vel, m, 1e-5, act, mode)
     for x, y in zip(r1, r2):
         np.testing.assert_array_equal(x, y)
 

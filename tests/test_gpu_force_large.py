@@ -3,9 +3,13 @@
 The GPU evaluates the whole active block in the launch configuration the
 benchmark times (the tuned N = 2^20 table is installed as the benchmark
 installs it: its n_i = N entry is also the block-step launch's shape); the
-oracle evaluates 4096 sampled particles of it (one by one over all 2^20 j).  Gates: float32 tile sums p99 <= 1e-5; the
-compensated sums must not be worse than the float32 sums and stay within
-the float32 pair-arithmetic floor (p99 <= 1e-6).
+oracle evaluates 4096 sampled particles of it (one by one over all 2^20 j).
+Gates on the per-particle relative error over all 4096 samples: float32
+mode acceleration p99 <= 1e-7 and max <= 1e-6 (at this N the many distant
+pairs dominate and the float32 tile sums, added in float64, stay near the
+float32 rounding of the pair terms), jerk p99 <= 5e-6 and max <= 1e-5;
+compensated mode (float64 pair terms) acceleration and jerk p99 <= 1e-12
+and max <= 1e-11.
 """
 import numpy as np
 import pytest
@@ -59,7 +63,7 @@ def test_sampled_accuracy(orc, big, tuned, n_i):
     ref = orc.force(pos, vel, m, cfg.eps2, active=sample)
     P, V, M = dev(pos), dev(vel), dev(m)
     A = None if act is None else dev(act, torch.int32)
-    errs = {}
+    gates = {"fp32": (1e-7, 1e-6, 5e-6, 1e-5), "ds": (1e-12, 1e-11, 1e-12, 1e-11)}
     for mode in ("fp32", "ds"):
         acc, jerk, pot = nb.force(P, V, M, cfg.eps2, A, mode)
         acc, jerk, pot = host(acc)[:, slots], host(jerk)[:, slots], host(pot)[slots]
@@ -67,10 +71,12 @@ def test_sampled_accuracy(orc, big, tuned, n_i):
         ej = rel_vec_err(jerk, ref[1])
         ep = np.abs(pot - ref[2]) / np.abs(ref[2])
         glob = np.sqrt(((acc - ref[0]) ** 2).sum() / (ref[0] ** 2).sum())
-        errs[mode] = (np.percentile(ea, 99), glob)
         say("N=2^20 n_i=%d %s: acc p50 %.2e p99 %.2e max %.2e global %.2e | jerk p50 %.2e p99 %.2e"
-            " | pot p99 %.2e" % (n_i, mode, np.median(ea), np.percentile(ea, 99), ea.max(), glob,
-                                 np.median(ej), np.percentile(ej, 99), np.percentile(ep, 99)))
-    assert errs["fp32"][0] <= 1e-5
-    assert errs["ds"][0] <= 1e-6
-    assert errs["ds"][1] <= errs["fp32"][1] * 1.05
+            " max %.2e | pot p99 %.2e" % (n_i, mode, np.median(ea), np.percentile(ea, 99), ea.max(),
+                                          glob, np.median(ej), np.percentile(ej, 99), ej.max(),
+                                          np.percentile(ep, 99)))
+        a99, amax, j99, jmax = gates[mode]
+        assert np.percentile(ea, 99) <= a99
+        assert ea.max() <= amax
+        assert np.percentile(ej, 99) <= j99
+        assert ej.max() <= jmax

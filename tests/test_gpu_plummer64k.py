@@ -6,11 +6,13 @@ selects the block (t_i + dt_i minimal, Section 2), predicts every particle
 to the block time and evaluates the pair sums of up to 4096 seeded block
 members in float64 (Eq. 1 with Plummer softening).  After the GPU's step
 the new acceleration and jerk of those members (the corrector stores the
-pair sums at the predicted state) are compared with the oracle's.  Gates:
-acceleration p99 relative error <= 1e-5 with float32 accumulation and
-<= 1e-6 with compensated accumulation (float32 pair arithmetic bounds the
-latter at this N, where single close pairs dominate the error), same block
-as the oracle.  Energy: at eta = 0.02 the float64 oracle's own run of this
+pair sums at the predicted state) are compared with the oracle's.  Gates on
+the per-particle relative errors over all sampled members (the block
+members are the particles in the closest encounters, whose sums are
+dominated by one or two pairs and often cancel): float32 mode acceleration
+p99 <= 1e-6 and max <= 1e-5, jerk p99 <= 1e-5 and max <= 1e-4; compensated
+mode (float64 pair terms) acceleration and jerk p99 <= 1e-11 and max
+<= 1e-9; same block as the oracle.  Energy: at eta = 0.02 the float64 oracle's own run of this
 workload drifts by 1.68e-5 per time unit (Hermite truncation error, stored
 in tests/golden/plummer64k_run.json by make_plummer64k_run.py), above the
 1e-6 target, so the GPU's drift is gated against the oracle's: within
@@ -27,7 +29,8 @@ from workloads.plummer import CONFIGS, plummer
 
 pytestmark = pytest.mark.gpu
 
-TOL = {"fp32": 1e-5, "ds": 1e-6}
+# mode: (acc p99, acc max, jerk p99, jerk max)
+GATES = {"fp32": (1e-6, 1e-5, 1e-5, 1e-4), "ds": (1e-11, 1e-9, 1e-11, 1e-9)}
 GOLDEN = os.path.join(os.path.dirname(__file__), "golden", "plummer64k_run.json")
 
 
@@ -73,13 +76,15 @@ def test_plummer64k_sampled_blocks_and_drift(orc, mode):
     drift = abs((e1 - e0) / e0) / cfg.t_end
     ea, ek = np.concatenate(ea), np.concatenate(ek)
     say("plummer64k %s: %d steps, %d sampled blocks (mean size %.0f), acc median %.2e "
-        "p99 %.2e max %.2e, jerk median %.2e p99 %.2e, drift/unit %.2e"
+        "p99 %.2e max %.2e, jerk median %.2e p99 %.2e max %.2e, drift/unit %.2e"
         % (mode, steps, len(sizes), np.mean(sizes), np.median(ea), np.percentile(ea, 99),
-           ea.max(), np.median(ek), np.percentile(ek, 99), drift))
+           ea.max(), np.median(ek), np.percentile(ek, 99), ek.max(), drift))
     ref = json.load(open(GOLDEN))
     say("oracle run: %d steps, drift/unit %.4e" % (ref["steps"], ref["drift_per_time_unit"]))
     assert len(sizes) >= 10
-    assert np.percentile(ea, 99) <= TOL[mode]
+    a99, amax, j99, jmax = GATES[mode]
+    assert np.percentile(ea, 99) <= a99 and ea.max() <= amax
+    assert np.percentile(ek, 99) <= j99 and ek.max() <= jmax
     d_ref = ref["drift_per_time_unit"]
     assert abs(drift - d_ref) <= 1e-7 + 0.05 * d_ref
     assert abs(steps - ref["steps"]) <= 0.03 * ref["steps"]
