@@ -115,6 +115,27 @@ int nbody_force(nbody_ctx *ctx, const int32_t *active_idx, int64_t n_i,
                 int64_t n_j, double eps2, double *acc, double *jerk,
                 double *pot, uint32_t flags);
 
+/* ---- pair sums without allocation ----------------------------------------
+ * For callers that cannot allocate device memory: code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc.  Same
+ * arguments, arithmetic and errors as nbody_force, but the j records and the
+ * split partial sums live in a static array of NBODY_NOALLOC_SCRATCH_MB MiB
+ * that every device the library runs on holds until the process ends; the
+ * call makes no hipMalloc / hipFree and records no timing events (the
+ * context itself, including its status word, is allocated by nbody_create).
+ * The j split is capped so that the partial sums fit next to the records,
+ * so the launch shape (and the last bits of the float32 sums) can differ
+ * from nbody_force's for large n_i.
+ *   n_j : 1 <= n_j <= NBODY_NOALLOC_MAX_NJ, else NBODY_E_INVAL (host check).
+ * Every call on a device shares that device's array: calls that overlap on
+ * one device (other streams, other threads, other contexts) race. */
+#define NBODY_NOALLOC_SCRATCH_MB 96
+#define NBODY_NOALLOC_MAX_NJ 1048576
+int nbody_force_noalloc(nbody_ctx *ctx, const int32_t *active_idx, int64_t n_i,
+                        const double *pos, const double *vel, const double *mass,
+                        int64_t n_j, double eps2, double *acc, double *jerk,
+                        double *pot, uint32_t flags);
+
 /* ---- predictor ---------------------------------------------------------
  * Section 2: for every particle, with h = t_target - t[i],
  *   xp = x + (v + (h/2)(a + (h/3) k)) h,    vp = v + (a + (h/2) k) h

@@ -23,7 +23,7 @@ import torch
 from . import _lib as L
 
 __all__ = [
-    "NBodyError", "Context", "context", "force", "predict", "schedule",
+    "NBodyError", "Context", "context", "force", "force_noalloc", "predict", "schedule",
     "correct", "initial_dt", "energy", "System", "ACC_FP32", "ACC_DS",
     "ForceShape", "tune_set", "tune_clear", "tune_get", "profile",
     "force_adjoint", "predict_adjoint", "correct_adjoint", "ensemble_run",
@@ -166,6 +166,34 @@ def force(pos, vel, mass, eps2, active_idx=None, mode="fp32", out=None):
     ctx.check(ctx.lib.nbody_force(ctx.bind(), _ptr(active_idx), n_i, _ptr(pos), _ptr(vel),
                                   _ptr(mass), n, float(eps2), _ptr(acc), _ptr(jerk),
                                   _ptr(pot), _mode(mode)))
+    return acc, jerk, pot
+
+
+def force_noalloc(pos, vel, mass, eps2, active_idx=None, mode="fp32", out=None):
+    """As force(), through nbody_force_noalloc: the library allocates no
+    device memory for the call (its scratch is a static per-device array).
+    Pass preallocated (acc, jerk, pot) as `out` to allocate nothing at all;
+    n must not exceed NBODY_NOALLOC_MAX_NJ."""
+    n = mass.shape[0]
+    _vec(pos, n, "pos"), _vec(vel, n, "vel"), _sca(mass, n, "mass")
+    if active_idx is not None:
+        if active_idx.dtype != torch.int32 or not active_idx.is_cuda or active_idx.dim() != 1 \
+                or not active_idx.is_contiguous():
+            raise ValueError("active_idx must be a contiguous 1-d int32 CUDA tensor")
+        n_i = active_idx.shape[0]
+    else:
+        n_i = n
+    if out is None:
+        acc = torch.empty((3, n_i), dtype=torch.float64, device=pos.device)
+        jerk = torch.empty_like(acc)
+        pot = torch.empty((n_i,), dtype=torch.float64, device=pos.device)
+    else:
+        acc, jerk, pot = out
+        _vec(acc, n_i, "acc"), _vec(jerk, n_i, "jerk"), _sca(pot, n_i, "pot")
+    ctx = context(pos.device)
+    ctx.check(ctx.lib.nbody_force_noalloc(ctx.bind(), _ptr(active_idx), n_i, _ptr(pos),
+                                          _ptr(vel), _ptr(mass), n, float(eps2), _ptr(acc),
+                                          _ptr(jerk), _ptr(pot), _mode(mode)))
     return acc, jerk, pot
 
 

@@ -23,6 +23,7 @@ NBODY_ACC_FP32 = 0
 NBODY_ACC_DS = 1
 NBODY_FIXED_DT = 2
 NBODY_ADJ_ACCUMULATE = 4
+NBODY_NOALLOC_MAX_NJ = 1048576
 
 P = ctypes.c_void_p
 I64 = ctypes.c_int64
@@ -69,6 +70,7 @@ SIGNATURES = {
     "nbody_last_error": (ctypes.c_char_p, [P]),
     "nbody_sync_status": (INT, [P]),
     "nbody_force": (INT, [P, P, I64, P, P, P, I64, D, P, P, P, U32]),
+    "nbody_force_noalloc": (INT, [P, P, I64, P, P, P, I64, D, P, P, P, U32]),
     "nbody_predict": (INT, [P, I64, D, P, P, P, P, P, P, P]),
     "nbody_schedule": (INT, [P, I64, P, P, P, P, P]),
     "nbody_correct": (INT, [P, I64, I64, P, P, P, P, P, D, D, D, INT, P, P, P, P,

@@ -80,6 +80,8 @@ struct nbody_ctx {
     size_t chain_bytes = 0;
     void *ens = nullptr;  // ensemble tables and team scratch
     size_t ens_bytes = 0;
+    void *static_scratch = nullptr;  // this device's copy of the static scratch
+    int static_scratch_rc = 0;       // hipGetSymbolAddress status (hipError_t)
     nbody_ensemble_config ens_cfg = {2, 64, 30.0, 15.0, 0.5, 2.0e9, 247.0, 0.35};
     int ens_last_grid = 0;
     int ens_last_teams = 0;
@@ -131,12 +133,21 @@ struct ForceCall {
     double *acc = nullptr, *jerk = nullptr, *pot = nullptr;
     int64_t out_stride = 0;
     int mode = 0;  // accumulation, ACC_* (pairs.hpp)
+    // Caller-provided partial-sum buffer (static scratch): when set, the j
+    // split is capped at max_splits so that the partials fit in part_cap
+    // bytes, nothing is allocated and no timing events are recorded.
+    void *part_buf = nullptr;
+    size_t part_cap = 0;
+    int max_splits = 0;  // 0: the library's limit
 };
 int launch_force(nbody_ctx *ctx, const ForceCall &c);
 int launch_pack(nbody_ctx *ctx, int rep, int64_t n, const double *pos,
                 const double *vel, const double *mass, JRec *out);
 // Shape used by the block-step driver (block size known only on the device).
 ForceShape dynamic_shape(const nbody_ctx *ctx, int64_t n);
+// Address of the static scratch array on the context's device (called by
+// nbody_create with that device current; sets static_scratch(_rc)).
+void static_scratch_setup(nbody_ctx *ctx);
 
 }  // namespace nb
 

@@ -137,6 +137,7 @@ int nbody_create(nbody_ctx **out, int device, void *stream) {
                 hipSuccess && cus > 0)
             ctx->cus = cus;
         rc = ensure_info(ctx);
+        if (rc == NBODY_OK) static_scratch_setup(ctx);
     }
     if (rc != NBODY_OK) {
         nbody_destroy(ctx);

@@ -587,7 +587,7 @@ int launch_force(nbody_ctx *ctx, const ForceCall &c) {
     a.tile = sh.tile;
     a.min_j_wave = sh.min_j_wave;
     a.target_groups = sh.target_groups;
-    a.max_splits = kMaxSplits;
+    a.max_splits = c.max_splits > 0 && c.max_splits < kMaxSplits ? c.max_splits : kMaxSplits;
     a.accumulate = 0;
     a.part_f32 = c.mode == ACC_F32 ? 1 : 0;
     const int64_t part_elem = a.part_f32 ? (int64_t)sizeof(float) : (int64_t)sizeof(double);
@@ -626,10 +626,17 @@ int launch_force(nbody_ctx *ctx, const ForceCall &c) {
         need_part = S > 1 ? S * 7 * c.n_i * part_elem : 0;
         if (items > (1 << 24)) items = 1 << 24;
     }
-    const bool prof = ctx->prof.on;
+    const bool prof = ctx->prof.on && !c.part_buf;
     if (need_part > 0) {
-        NB_TRY(ensure(ctx, &ctx->part, &ctx->part_bytes, (size_t)need_part));
-        a.part = (double *)ctx->part;
+        if (c.part_buf) {
+            if ((size_t)need_part > c.part_cap)
+                return fail(ctx, NBODY_E_INVAL, "partial sums need %lld bytes, %zu available",
+                            (long long)need_part, c.part_cap);
+            a.part = (double *)c.part_buf;
+        } else {
+            NB_TRY(ensure(ctx, &ctx->part, &ctx->part_bytes, (size_t)need_part));
+            a.part = (double *)ctx->part;
+        }
     }
     hipEvent_t e0 = prof ? prof_mark(ctx) : nullptr;
     hipLaunchKernelGGL(fn, dim3((unsigned)items), dim3(64 * sh.waves), 0, ctx->stream, a);
