@@ -394,7 +394,14 @@ int nbody_shared_run_adjoint(nbody_ctx *ctx, int64_t n, const double *m, double 
  *                 (at most 4 with 4 i-particles per lane).
  *   tile          j-particles summed in float32 before each fold (>= 1).
  *   min_j_wave    smallest j range per wave when the j range is split (>= 1).
- *   target_groups workgroups to aim for before splitting j (>= 1). */
+ *   target_groups workgroups to aim for before splitting j (>= 1).
+ *   layout        0: one i-particle per lane, every j broadcast to the wave;
+ *                 1: one j-particle per lane (vector loads), the workgroup's
+ *                 i_per_lane (1, 2, 4 or 8; at most 4 with NBODY_ACC_DS)
+ *                 i-particles shared by all lanes, lane sums added by a
+ *                 fixed-order butterfly -- for small active blocks.  Layout 1
+ *                 takes rep 0 and 1, 2 or 4 waves; `tile` bounds the terms of
+ *                 a lane's float32 sum. */
 typedef struct nbody_force_config {
     int32_t rep;
     int32_t i_per_lane;
@@ -402,12 +409,15 @@ typedef struct nbody_force_config {
     int32_t tile;
     int32_t min_j_wave;
     int32_t target_groups;
+    int32_t layout;
 } nbody_force_config;
 
-/* Use `cfg` for active-block sizes n_i in [n_i_lo, n_i_hi).  n_i_lo < 0
+/* Use `cfg` for active-block sizes n_i in [n_i_lo, n_i_hi).  n_i_lo = -1
  * sets the shape of the block-step driver's pair launches (block size known
- * only on the device).  Later entries do not override earlier ones that
- * cover the same n_i.  NBODY_E_INVAL for an unsupported shape. */
+ * only on the device); n_i_lo = -2 sets the driver's small-block shape (a
+ * layout-1 shape) and n_i_hi its largest block, i.e. blocks of up to n_i_hi
+ * particles take that shape (n_i_hi = 0: no small-block shape).  Later entries do not override earlier ones
+ * that cover the same n_i.  NBODY_E_INVAL for an unsupported shape. */
 int nbody_tune_set(nbody_ctx *ctx, int64_t n_i_lo, int64_t n_i_hi,
                    const nbody_force_config *cfg);
 /* Timing of the pair kernels with HIP events recorded on the context's

@@ -418,11 +418,12 @@ def ensemble_plan(sizes, groups, t_end, config):
 class ForceShape(tuple):
     """Launch shape of the pair kernels (see nbody_force_config)."""
     __slots__ = ()
-    _names = ("rep", "i_per_lane", "waves", "tile", "min_j_wave", "target_groups")
+    _names = ("rep", "i_per_lane", "waves", "tile", "min_j_wave", "target_groups", "layout")
 
-    def __new__(cls, rep=0, i_per_lane=2, waves=1, tile=128, min_j_wave=64, target_groups=32768):
+    def __new__(cls, rep=0, i_per_lane=2, waves=1, tile=128, min_j_wave=64, target_groups=32768,
+                layout=0):
         return tuple.__new__(cls, (int(rep), int(i_per_lane), int(waves), int(tile),
-                                   int(min_j_wave), int(target_groups)))
+                                   int(min_j_wave), int(target_groups), int(layout)))
 
     def asdict(self):
         return dict(zip(self._names, self))
@@ -432,8 +433,9 @@ class ForceShape(tuple):
 
 
 def tune_set(n_i_lo, n_i_hi, shape, device=None):
-    """Use `shape` for active blocks of n_i in [n_i_lo, n_i_hi); n_i_lo < 0
-    sets the block-step driver's shape."""
+    """Use `shape` for active blocks of n_i in [n_i_lo, n_i_hi); n_i_lo = -1
+    sets the block-step driver's shape, n_i_lo = -2 its small-block shape
+    (layout 1) for blocks of up to n_i_hi particles."""
     ctx = context(device)
     c = L.NBodyForceConfig(*shape)
     ctx.check(ctx.lib.nbody_tune_set(ctx.h, int(n_i_lo), int(n_i_hi), ctypes.byref(c)))
@@ -448,7 +450,8 @@ def tune_get(n_i, device=None) -> ForceShape:
     ctx = context(device)
     c = L.NBodyForceConfig()
     ctx.check(ctx.lib.nbody_tune_get(ctx.h, int(n_i), ctypes.byref(c)))
-    return ForceShape(c.rep, c.i_per_lane, c.waves, c.tile, c.min_j_wave, c.target_groups)
+    return ForceShape(c.rep, c.i_per_lane, c.waves, c.tile, c.min_j_wave, c.target_groups,
+                      c.layout)
 
 
 def profile(enable=-1, device=None):

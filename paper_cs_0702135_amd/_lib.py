@@ -44,7 +44,7 @@ class NBodySystem(ctypes.Structure):
 class NBodyForceConfig(ctypes.Structure):
     """Mirror of ``nbody_force_config`` in include/nbody.h."""
     _fields_ = [("rep", I32), ("i_per_lane", I32), ("waves", I32), ("tile", I32),
-                ("min_j_wave", I32), ("target_groups", I32)]
+                ("min_j_wave", I32), ("target_groups", I32), ("layout", I32)]
 
 
 class NBodyEnsemble(ctypes.Structure):

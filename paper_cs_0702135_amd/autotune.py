@@ -40,8 +40,19 @@ def cache_path(n_j: int, mode: str) -> str:
     return os.path.join(CACHE_DIR, "%s_nj%d_%s.json" % (arch, _bucket(n_j), mode))
 
 
+JL_MAX_TRY = 512  # largest block given j-lane candidates
+
+
 def candidates(n_i: int, n_j: int, forms=(0,)):
     out = []
+    if n_i <= JL_MAX_TRY:
+        # one j per lane, the workgroup's C i-particles shared by all lanes
+        for c in (1, 2, 4, 8):
+            if c > 1 and c > 2 * n_i:
+                continue
+            for w in (1, 2, 4):
+                for tg in (256, 512, 2048, 8192):
+                    out.append(ForceShape(0, c, w, 128, 64, tg, 1))
     for rep in forms:
         for it in (1, 2, 4):
             if n_i <= 64 and it > 1:
@@ -117,6 +128,15 @@ def install(table, dynamic_n_i=None):
         target = dynamic_n_i or (sizes[1] if len(sizes) > 1 else sizes[0])
         pick = min(ent, key=lambda e: abs(math.log2(e[0]) - math.log2(max(1, target))))
         tune_set(-1, 0, ForceShape(**pick[1]))
+        # the driver's small blocks: the j-lane shape of the largest of the
+        # smallest measured sizes that all chose it, up to the midpoint with
+        # the next size
+        k = 0
+        while k < len(ent) and ent[k][1].get("layout", 0) == 1:
+            k += 1
+        if k > 0 and pick[1].get("layout", 0) == 0:
+            jl_max = int(math.sqrt(sizes[k - 1] * sizes[k])) if k < len(ent) else sizes[k - 1]
+            tune_set(-2, jl_max, ForceShape(**ent[k - 1][1]))
 
 
 def load(n_j, mode="fp32"):

@@ -32,14 +32,16 @@ struct StepInfo {
 
 enum : int32_t { ST_RANGE = 1, ST_NONFINITE = 2, ST_INDEX = 4 };
 
-// Tunable launch shape of the pair kernel.
+// Tunable launch shape of the pair kernels.
 struct ForceShape {
     int rep = REP_F64;     // form of the relative coordinates (REP_*)
-    int it = 1;            // i-particles per lane (1 or 2)
+    int it = 1;            // i-particles per lane (i-lanes: 1, 2, 4; j-lanes: 1, 2, 4, 8)
     int waves = 4;         // waves per workgroup (split j inside the group)
     int tile = 128;        // j per float32 inner sum before folding
     int min_j_wave = 64;   // smallest j range per wave when splitting j
     int target_groups = 4096;  // workgroups to aim for before splitting j
+    int layout = 0;        // 0: one i per lane (force_kernel); 1: one j per lane
+                           // (force_jl_kernel), the `it` i-particles wave-uniform
 };
 
 struct TuneEntry {
@@ -133,6 +135,10 @@ struct ForceCall {
     double *acc = nullptr, *jerk = nullptr, *pot = nullptr;
     int64_t out_stride = 0;
     int mode = 0;  // accumulation, ACC_* (pairs.hpp)
+    // Device-counted launches only: blocks of at most jl_max particles take
+    // the j-lane kernel in shape jl_shape (0: none).
+    ForceShape jl_shape;
+    int64_t jl_max = 0;
     // Caller-provided partial-sum buffer (static scratch): when set, the j
     // split is capped at max_splits so that the partials fit in part_cap
     // bytes, nothing is allocated and no timing events are recorded.
@@ -145,6 +151,9 @@ int launch_pack(nbody_ctx *ctx, int rep, int64_t n, const double *pos,
                 const double *vel, const double *mass, JRec *out);
 // Shape used by the block-step driver (block size known only on the device).
 ForceShape dynamic_shape(const nbody_ctx *ctx, int64_t n);
+// The driver's small-block shape (j-lane layout) and the largest block it
+// takes (*jl_max = 0: none) for a system of n particles.
+ForceShape dynamic_small_shape(const nbody_ctx *ctx, int64_t n, int64_t *jl_max);
 // Address of the static scratch array on the context's device (called by
 // nbody_create with that device current; sets static_scratch(_rc)).
 void static_scratch_setup(nbody_ctx *ctx);

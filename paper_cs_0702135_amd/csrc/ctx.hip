@@ -197,12 +197,20 @@ int nbody_sync_status(nbody_ctx *ctx) {
 
 static int shape_ok(const nbody_force_config *c) {
     if (!c) return 0;
+    if (c->tile < 1 || c->min_j_wave < 1 || c->target_groups < 1) return 0;
+    if (c->target_groups > (1 << 20)) return 0;
+    if (c->layout == 1) {
+        // j-lane kernel: float64 records, 1/2/4/8 i-particles, 1/2/4 waves
+        if (c->rep != REP_F64) return 0;
+        if (c->i_per_lane != 1 && c->i_per_lane != 2 && c->i_per_lane != 4 && c->i_per_lane != 8)
+            return 0;
+        return c->waves == 1 || c->waves == 2 || c->waves == 4;
+    }
+    if (c->layout != 0) return 0;
     if (c->rep < REP_F64 || c->rep > REP_F64V) return 0;
     if (c->i_per_lane != 1 && c->i_per_lane != 2 && c->i_per_lane != 4) return 0;
     if (c->waves != 1 && c->waves != 2 && c->waves != 4 && c->waves != 8) return 0;
     if (c->i_per_lane == 4 && c->waves == 8) return 0;
-    if (c->tile < 1 || c->min_j_wave < 1 || c->target_groups < 1) return 0;
-    if (c->target_groups > (1 << 20)) return 0;
     return 1;
 }
 
@@ -212,8 +220,11 @@ int nbody_tune_set(nbody_ctx *ctx, int64_t n_i_lo, int64_t n_i_hi,
     if (!shape_ok(cfg)) return fail(ctx, NBODY_E_INVAL, "nbody_tune_set: unsupported shape");
     if (n_i_lo >= 0 && n_i_hi <= n_i_lo)
         return fail(ctx, NBODY_E_INVAL, "nbody_tune_set: empty range");
+    if (n_i_lo == -2 && (cfg->layout != 1 || n_i_hi < 0))
+        return fail(ctx, NBODY_E_INVAL,
+                    "nbody_tune_set: the small-block entry needs layout 1 and n_i_hi >= 0");
     TuneEntry e;
-    e.n_i_lo = n_i_lo < 0 ? -1 : n_i_lo;
+    e.n_i_lo = n_i_lo == -2 ? -2 : (n_i_lo < 0 ? -1 : n_i_lo);
     e.n_i_hi = n_i_hi;
     e.shape.rep = cfg->rep;
     e.shape.it = cfg->i_per_lane;
@@ -221,6 +232,7 @@ int nbody_tune_set(nbody_ctx *ctx, int64_t n_i_lo, int64_t n_i_hi,
     e.shape.tile = cfg->tile;
     e.shape.min_j_wave = cfg->min_j_wave;
     e.shape.target_groups = cfg->target_groups;
+    e.shape.layout = cfg->layout;
     ctx->tune.push_back(e);
     return NBODY_OK;
 }
@@ -291,13 +303,20 @@ int nbody_tune_clear(nbody_ctx *ctx) {
 
 int nbody_tune_get(nbody_ctx *ctx, int64_t n_i, nbody_force_config *out) {
     if (!ctx || !out) return NBODY_E_INVAL;
-    const ForceShape s = n_i < 0 ? dynamic_shape(ctx, 0) : pick_shape(ctx, n_i, 0);
+    ForceShape s;
+    if (n_i == -2) {
+        int64_t jl_max = 0;
+        s = dynamic_small_shape(ctx, 0, &jl_max);
+    } else {
+        s = n_i < 0 ? dynamic_shape(ctx, 0) : pick_shape(ctx, n_i, 0);
+    }
     out->rep = s.rep;
     out->i_per_lane = s.it;
     out->waves = s.waves;
     out->tile = s.tile;
     out->min_j_wave = s.min_j_wave;
     out->target_groups = s.target_groups;
+    out->layout = s.layout;
     return NBODY_OK;
 }
 

@@ -160,7 +160,7 @@ __global__ __launch_bounds__(64 * W) void force_kernel(const KArgs a) {
     typedef typename F::Rec Rec;
     static_assert(ACC != ACC_F64 || REP == REP_F64, "float64 pair terms need float64 records");
     const int64_t n_i = a.n_i_dev ? *a.n_i_dev : a.n_i;
-    if (n_i <= 0) return;
+    if (n_i <= 0 || n_i <= a.jl_max) return;  // (j-lane kernel's blocks)
     const int n_j = a.n_j;
     const int64_t ostride = a.out_stride > 0 ? a.out_stride : n_i;
     const int lane = threadIdx.x & 63;
@@ -400,6 +400,219 @@ __global__ __launch_bounds__(64 * W) void force_kernel(const KArgs a) {
     }
 }
 
+// j-lane layout for small active blocks.  With few i-particles the i-lane
+// kernel leaves most lanes idle and each wave walks its j range as a chain of
+// dependent scalar loads; here the C i-particles of a workgroup are
+// wave-uniform (scalar registers) and every lane takes its own j, fetched
+// with coalesced vector loads (64 consecutive records per wave and step).
+// A lane sums its j terms in float32 (at most `tile` of them, see
+// choose_splits_jl) or float64; the lane sums are added in float64 by a
+// fixed-order butterfly over the wave, the waves' totals in wave order
+// through LDS, and the splits by reduce_parts_kernel.  Lanes past the end of
+// the range and the self pair are masked (only in the 64-j steps that can
+// contain them).
+template <int C, int W, int ACC>
+__global__ __launch_bounds__(64 * W) void force_jl_kernel(const KArgs a) {
+    const int64_t n_i = a.n_i_dev ? *a.n_i_dev : a.n_i;
+    if (n_i <= 0 || n_i > a.jl_max) return;  // (i-lane kernel's blocks)
+    const int n_j = a.n_j;
+    const int64_t ostride = a.out_stride > 0 ? a.out_stride : n_i;
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int64_t nb = (n_i + C - 1) / C;
+    const int64_t S = choose_splits_jl(n_i, n_j, C, W, a.jl_tile, a.jl_min_j_wave,
+                                       a.jl_target_groups, a.max_splits);
+    const int64_t items = nb * S;
+    const int64_t jchunk = (n_j + S - 1) / S;
+    const float eps2 = a.eps2;
+    const double eps2d = a.eps2d;
+    const RecF64 *__restrict__ R = (const RecF64 *)a.jrec;
+
+    __shared__ double red[W > 1 ? W - 1 : 1][7 * C];
+
+    for (int64_t q = blockIdx.x; q < items; q += gridDim.x) {
+        const int64_t item = xcd_item(q, items);
+        const int64_t ib = item % nb;
+        const int64_t sp = item / nb;
+        const int j0 = (int)(sp * jchunk);
+        const int j1 = (int)min((int64_t)n_j, (int64_t)j0 + jchunk);
+        // wave ranges in whole steps of 64 j
+        const int jw = (((j1 - j0 + W - 1) / W) + 63) & ~63;
+        const int jb = __builtin_amdgcn_readfirstlane(min(j1, j0 + wave * jw));
+        const int je = __builtin_amdgcn_readfirstlane(min(j1, jb + jw));
+
+        // the workgroup's i-particles, wave-uniform: read through the
+        // constant address space, so with scalar loads into SGPRs
+        int idx[C];
+        double xi[C], yi[C], zi[C], ui[C], vi[C], wi[C];
+        const CONSTP(int32_t) Act = (CONSTP(int32_t))a.active;
+        const CONSTP(double) Pos = (CONSTP(double))a.pos;
+        const CONSTP(double) Vel = (CONSTP(double))a.vel;
+#pragma unroll
+        for (int c = 0; c < C; ++c) {
+            const int64_t slot = ib * C + c;
+            const int64_t sl = slot < n_i ? slot : n_i - 1;
+            const int raw = Act ? Act[sl] : (int)sl;
+            const bool bad = (unsigned)raw >= (unsigned)n_j;
+            if (bad && lane == 0) atomicOr(a.status, (int32_t)ST_INDEX);
+            const int id = __builtin_amdgcn_readfirstlane(bad ? 0 : raw);
+            idx[c] = id;
+            xi[c] = Pos[id];
+            yi[c] = Pos[n_j + (int64_t)id];
+            zi[c] = Pos[2 * (int64_t)n_j + id];
+            ui[c] = Vel[id];
+            vi[c] = Vel[n_j + (int64_t)id];
+            wi[c] = Vel[2 * (int64_t)n_j + id];
+        }
+
+        // per-lane sums; the potential as +sum m/r (negated when stored)
+        float s32[C][7];
+        double s64[C][7];
+#pragma unroll
+        for (int c = 0; c < C; ++c)
+#pragma unroll
+            for (int k = 0; k < 7; ++k) {
+                s32[c][k] = 0.0f;
+                s64[c][k] = 0.0;
+            }
+
+        auto body = [&](const RecF64 &r, const int j, const bool mask)
+            __attribute__((always_inline)) {
+            const bool dead_j = j >= je;
+#pragma unroll
+            for (int c = 0; c < C; ++c) {
+                if constexpr (ACC == ACC_F64) {
+                    const double dx = r.x - xi[c], dy = r.y - yi[c], dz = r.z - zi[c];
+                    const double du = r.u - ui[c], dv = r.v - vi[c], dw = r.w - wi[c];
+                    double s2 = fma(dz, dz, fma(dy, dy, fma(dx, dx, eps2d)));
+                    double mj = r.md;
+                    if (mask) {
+                        const bool dead = dead_j || j == idx[c];
+                        s2 = dead ? 1.0 : s2;
+                        mj = dead ? 0.0 : mj;
+                    }
+                    const double rv = fma(dz, dw, fma(dy, dv, dx * du));
+                    const double y0 = (double)__builtin_amdgcn_rsqf((float)s2);
+                    const double e = fma(-(s2 * y0), y0, 1.0);
+                    const double y = fma(0.5 * y0, e, y0);
+                    const double y2 = y * y;
+                    const double mr3 = (mj * y) * y2;
+                    const double w3 = (rv * y2) * -3.0;
+                    s64[c][0] = fma(mr3, dx, s64[c][0]);
+                    s64[c][1] = fma(mr3, dy, s64[c][1]);
+                    s64[c][2] = fma(mr3, dz, s64[c][2]);
+                    s64[c][3] = fma(mr3, fma(w3, dx, du), s64[c][3]);
+                    s64[c][4] = fma(mr3, fma(w3, dy, dv), s64[c][4]);
+                    s64[c][5] = fma(mr3, fma(w3, dz, dw), s64[c][5]);
+                    s64[c][6] = fma(mj, y, s64[c][6]);
+                } else {
+                    const float dx = (float)(r.x - xi[c]), dy = (float)(r.y - yi[c]);
+                    const float dz = (float)(r.z - zi[c]);
+                    const float du = (float)(r.u - ui[c]), dv = (float)(r.v - vi[c]);
+                    const float dw = (float)(r.w - wi[c]);
+                    float s2 = fmaf(dz, dz, fmaf(dy, dy, fmaf(dx, dx, eps2)));
+                    float mj = r.m;
+                    if (mask) {
+                        const bool dead = dead_j || j == idx[c];
+                        s2 = dead ? 1.0f : s2;
+                        mj = dead ? 0.0f : mj;
+                    }
+                    const float rv = fmaf(dz, dw, fmaf(dy, dv, dx * du));
+                    const float rinv = __builtin_amdgcn_rsqf(s2);
+                    const float rinv2 = rinv * rinv;
+                    const float mr3 = (mj * rinv) * rinv2;
+                    const float w3 = (rv * rinv2) * -3.0f;
+                    s32[c][0] = fmaf(mr3, dx, s32[c][0]);
+                    s32[c][1] = fmaf(mr3, dy, s32[c][1]);
+                    s32[c][2] = fmaf(mr3, dz, s32[c][2]);
+                    s32[c][3] = fmaf(mr3, fmaf(w3, dx, du), s32[c][3]);
+                    s32[c][4] = fmaf(mr3, fmaf(w3, dy, dv), s32[c][4]);
+                    s32[c][5] = fmaf(mr3, fmaf(w3, dz, dw), s32[c][5]);
+                    s32[c][6] = fmaf(mj, rinv, s32[c][6]);
+                }
+            }
+        };
+        auto load = [&](int j) __attribute__((always_inline)) {
+            RecF64 r;
+            r.x = R[j].x; r.y = R[j].y; r.z = R[j].z;
+            r.u = R[j].u; r.v = R[j].v; r.w = R[j].w;
+            if constexpr (ACC == ACC_F64) r.md = R[j].md; else r.m = R[j].m;
+            return r;
+        };
+
+        if (jb < je) {
+            // the next step's records are in flight while this one is used
+            RecF64 cur = load(min(jb + lane, je - 1));
+            for (int jt = jb; jt < je; jt += 64) {
+                const RecF64 nxt = load(min(jt + 64 + lane, je - 1));
+                bool edge = jt + 64 > je;
+#pragma unroll
+                for (int c = 0; c < C; ++c) edge |= (unsigned)(idx[c] - jt) < 64u;
+                if (edge)
+                    body(cur, jt + lane, true);
+                else
+                    body(cur, jt + lane, false);
+                cur = nxt;
+            }
+        }
+
+        // lane sums -> wave totals (float64 butterfly, fixed order)
+        double tot[C][7];
+#pragma unroll
+        for (int c = 0; c < C; ++c)
+#pragma unroll
+            for (int k = 0; k < 7; ++k) {
+                double v = ACC == ACC_F64 ? s64[c][k] : (double)s32[c][k];
+#pragma unroll
+                for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
+                tot[c][k] = v;
+            }
+        if (W > 1) {
+            if (wave > 0 && lane == 0) {
+#pragma unroll
+                for (int c = 0; c < C; ++c)
+#pragma unroll
+                    for (int k = 0; k < 7; ++k) red[wave - 1][c * 7 + k] = tot[c][k];
+            }
+            __syncthreads();
+            if (wave == 0) {
+                for (int w = 1; w < W; ++w)
+#pragma unroll
+                    for (int c = 0; c < C; ++c)
+#pragma unroll
+                        for (int k = 0; k < 7; ++k) tot[c][k] += red[w - 1][c * 7 + k];
+            }
+        }
+        if (wave == 0) {
+#pragma unroll
+            for (int c = 0; c < C; ++c) {
+                const int64_t slot = ib * C + c;
+                if (lane == c && slot < n_i) {
+                    tot[c][6] = -tot[c][6];
+                    if (S == 1) {
+                        a.acc[slot] = tot[c][0];
+                        a.acc[ostride + slot] = tot[c][1];
+                        a.acc[2 * ostride + slot] = tot[c][2];
+                        a.jerk[slot] = tot[c][3];
+                        a.jerk[ostride + slot] = tot[c][4];
+                        a.jerk[2 * ostride + slot] = tot[c][5];
+                        if (a.pot) a.pot[slot] = tot[c][6];
+                    } else if (!a.part_f32) {
+                        double *p = a.part + (sp * 7) * n_i + slot;
+#pragma unroll
+                        for (int k = 0; k < 7; ++k) p[k * n_i] = tot[c][k];
+                    } else {
+                        float *p = (float *)a.part + (sp * 7) * n_i + slot;
+#pragma unroll
+                        for (int k = 0; k < 7; ++k) p[k * n_i] = (float)tot[c][k];
+                    }
+                }
+            }
+        }
+        if (W > 1) __syncthreads();
+    }
+}
+
 // Adds the S float64 partial sums of every output in a fixed order: the 64
 // lanes of a wave take 64 consecutive outputs, the RW waves of a workgroup
 // take contiguous quarters of the splits, and the wave sums are combined in
@@ -408,8 +621,11 @@ __global__ __launch_bounds__(64 * RW) void reduce_parts_kernel(const KArgs a, in
     __shared__ double red[RW][64];
     const int64_t n_i = a.n_i_dev ? *a.n_i_dev : a.n_i;
     if (n_i <= 0) return;
-    const int64_t S = choose_splits(n_i, a.n_j, it, waves, a.min_j_wave, a.target_groups,
-                                    a.max_splits);
+    const int64_t S = n_i <= a.jl_max
+                          ? choose_splits_jl(n_i, a.n_j, a.jl_c, a.jl_waves, a.jl_tile,
+                                             a.jl_min_j_wave, a.jl_target_groups, a.max_splits)
+                          : choose_splits(n_i, a.n_j, it, waves, a.min_j_wave, a.target_groups,
+                                          a.max_splits);
     if (S == 1) return;
     const int64_t ostride = a.out_stride > 0 ? a.out_stride : n_i;
     const int64_t total = 7 * n_i;
@@ -498,15 +714,48 @@ static force_fn pick_kernel(const ForceShape &s, int acc) {
     }
 }
 
+template <int C, int ACC>
+static force_fn pick_jl_w(int w) {
+    switch (w) {
+        case 1: return force_jl_kernel<C, 1, ACC>;
+        case 2: return force_jl_kernel<C, 2, ACC>;
+        case 4: return force_jl_kernel<C, 4, ACC>;
+        default: return nullptr;
+    }
+}
+
+static force_fn pick_jl_kernel(const ForceShape &s, int acc) {
+    if (s.rep != REP_F64) return nullptr;
+    if (acc == ACC_F64) {
+        switch (s.it) {
+            case 1: return pick_jl_w<1, ACC_F64>(s.waves);
+            case 2: return pick_jl_w<2, ACC_F64>(s.waves);
+            case 4: return pick_jl_w<4, ACC_F64>(s.waves);
+            default: return nullptr;
+        }
+    }
+    switch (s.it) {
+        case 1: return pick_jl_w<1, ACC_F32>(s.waves);
+        case 2: return pick_jl_w<2, ACC_F32>(s.waves);
+        case 4: return pick_jl_w<4, ACC_F32>(s.waves);
+        case 8: return pick_jl_w<8, ACC_F32>(s.waves);
+        default: return nullptr;
+    }
+}
+
 int acc_mode(uint32_t flags) { return (flags & NBODY_ACC_DS) ? ACC_F64 : ACC_F32; }
 
 ForceShape shape_for(ForceShape s, int acc) {
+    if (s.layout == 1) s.rep = REP_F64;  // the j-lane kernel reads float64 records
     if (acc == ACC_F64) {
         s.rep = REP_F64;
-        if (s.it > 2) s.it = 2;
+        if (s.it > (s.layout == 1 ? 4 : 2)) s.it = s.layout == 1 ? 4 : 2;
     }
     return s;
 }
+
+// Largest active block the built-in shapes give to the j-lane kernel.
+constexpr int64_t kJlDefaultMax = 128;
 
 // Built-in shape for an active block of about n_i particles against n_j,
 // following what the autotuner and the block-step runs find on the MI355X:
@@ -522,6 +771,17 @@ ForceShape shape_for(ForceShape s, int acc) {
 // partial sums than they hide (64 j per wave).
 static ForceShape default_shape(const nbody_ctx *ctx, int64_t n_i, int64_t n_j) {
     ForceShape s;
+    if (n_i <= kJlDefaultMax && n_j > 8192) {
+        // small blocks of large systems: one j per lane (2.5x faster than
+        // one i per lane at n_i = 1 ... 64, N = 2^20; 2x at N = 65536)
+        s.layout = 1;
+        s.it = n_i <= 4 ? 1 : (n_i <= 16 ? 2 : 4);
+        s.waves = 4;
+        s.tile = 128;
+        s.min_j_wave = 64;
+        s.target_groups = 512;
+        return s;
+    }
     s.rep = REP_F64;
     s.it = n_i >= 256 ? 2 : 1;
     s.waves = n_i >= 1024 ? 2 : 4;
@@ -545,9 +805,30 @@ ForceShape pick_shape(const nbody_ctx *ctx, int64_t n_i, int64_t n_j) {
 // (resp. 4096), with 64 groups per CU, measured 6-8 % faster steps at
 // N = 16384 ... 65536 than the static rule (the same at 131072; slower at
 // 8192 and below, which keep it, as do larger systems, not measured).
+ForceShape dynamic_small_shape(const nbody_ctx *ctx, int64_t n, int64_t *jl_max) {
+    (void)n;
+    for (const TuneEntry &e : ctx->tune)
+        if (e.n_i_lo == -2) {
+            *jl_max = e.n_i_hi;
+            return e.shape;
+        }
+    // systems above 8192 particles: blocks of up to kJlDefaultMax take the
+    // j-lane kernel (below, a step is bound by launch latencies and the extra
+    // launch would not pay)
+    *jl_max = n > 8192 ? kJlDefaultMax : 0;
+    ForceShape s;
+    s.layout = 1;
+    s.it = 2;
+    s.waves = 4;
+    s.tile = 128;
+    s.min_j_wave = 64;
+    s.target_groups = 512;
+    return s;
+}
+
 ForceShape dynamic_shape(const nbody_ctx *ctx, int64_t n) {
     for (const TuneEntry &e : ctx->tune)
-        if (e.n_i_lo < 0) return e.shape;
+        if (e.n_i_lo == -1) return e.shape;
     const int64_t typ = (int64_t)(0.1 * std::pow((double)n, 0.9));
     ForceShape s = default_shape(ctx, typ, n);
     if (n > 8192 && n <= 131072) {
@@ -558,15 +839,68 @@ ForceShape dynamic_shape(const nbody_ctx *ctx, int64_t n) {
     return s;
 }
 
+// Upper bound of (i-blocks x splits) of the i-lane kernel over every block
+// size up to n_i_max, so that each item gets its own workgroup (dispatch
+// order = item order, which keeps the concurrently running groups on one or
+// two j chunks).
+static int64_t il_items_bound(const ForceShape &sh, int64_t n_i_max, int64_t n_j,
+                              int max_splits) {
+    const int64_t bi = 64 * sh.it;
+    const int64_t nb_max = (n_i_max + bi - 1) / bi;
+    int64_t smax = n_j / ((int64_t)sh.waves * sh.min_j_wave);
+    if (smax > max_splits) smax = max_splits;
+    if (smax < 1) smax = 1;
+    const int64_t tg = sh.target_groups;
+    int64_t a1 = (tg + smax - 1) / smax;  // below this nb, S = smax
+    if (a1 > nb_max) a1 = nb_max;
+    int64_t items = a1 * smax;
+    int64_t b2 = tg + nb_max;  // nb * ceil(tg / nb) < tg + nb
+    if (b2 > nb_max * smax) b2 = nb_max * smax;
+    if (b2 > items) items = b2;
+    if (nb_max > items) items = nb_max;
+    return items;
+}
+
+// The same for the j-lane kernel: nb * S <= tg + nb * s_lo and <= nb * smax.
+static int64_t jl_items_bound(const ForceShape &sh, int64_t n_i_max, int64_t n_j,
+                              int max_splits) {
+    const int64_t nb_max = (n_i_max + sh.it - 1) / sh.it;
+    const int64_t per_split = (int64_t)sh.waves * 64 * sh.tile;
+    const int64_t s_lo = (n_j + per_split - 1) / per_split;
+    int64_t smax = n_j / ((int64_t)sh.waves * sh.min_j_wave);
+    if (smax > max_splits) smax = max_splits;
+    if (smax < 1) smax = 1;
+    int64_t items = (int64_t)sh.target_groups + nb_max * s_lo;
+    if (items > nb_max * smax) items = nb_max * smax;
+    if (items < nb_max) items = nb_max;
+    return items;
+}
+
 int launch_force(nbody_ctx *ctx, const ForceCall &c) {
     const bool dev_count = c.n_i_dev != nullptr;
     const int64_t n_i_max = dev_count ? c.n_i_cap : c.n_i;
     if (n_i_max <= 0) return NBODY_OK;
-    const ForceShape &sh = c.shape;
-    force_fn fn = pick_kernel(sh, c.mode);
-    if (!fn)
-        return fail(ctx, NBODY_E_INVAL, "no pair kernel for rep=%d it=%d waves=%d acc=%d", sh.rep,
-                    sh.it, sh.waves, c.mode);
+    // Kernels: the shape's layout; a device-counted launch with jl_max > 0
+    // runs the j-lane kernel on blocks of up to jl_max particles and the
+    // i-lane kernel on larger ones (each returns early on the other's).
+    ForceShape il = c.shape, jl = c.shape;
+    bool use_il = true, use_jl = false;
+    int64_t jl_max = 0;
+    if (c.shape.layout == 1) {
+        use_il = false;
+        use_jl = true;
+        jl_max = INT64_MAX;
+    } else if (dev_count && c.jl_max > 0) {
+        use_jl = true;
+        jl = c.jl_shape;
+        jl_max = std::min(c.jl_max, n_i_max);
+    }
+    force_fn fil = use_il ? pick_kernel(il, c.mode) : nullptr;
+    force_fn fjl = use_jl ? pick_jl_kernel(jl, c.mode) : nullptr;
+    if ((use_il && !fil) || (use_jl && !fjl))
+        return fail(ctx, NBODY_E_INVAL, "no pair kernel for layout=%d rep=%d it=%d waves=%d acc=%d",
+                    use_jl && !fjl ? jl.layout : il.layout, use_jl && !fjl ? jl.rep : il.rep,
+                    use_jl && !fjl ? jl.it : il.it, use_jl && !fjl ? jl.waves : il.waves, c.mode);
 
     KArgs a;
     a.jrec = c.jrec;
@@ -584,48 +918,53 @@ int launch_force(nbody_ctx *ctx, const ForceCall &c) {
     a.n_j = (int32_t)c.n_j;
     a.eps2 = (float)c.eps2;
     a.eps2d = c.eps2;
-    a.tile = sh.tile;
-    a.min_j_wave = sh.min_j_wave;
-    a.target_groups = sh.target_groups;
+    a.tile = il.tile;
+    a.min_j_wave = il.min_j_wave;
+    a.target_groups = il.target_groups;
     a.max_splits = c.max_splits > 0 && c.max_splits < kMaxSplits ? c.max_splits : kMaxSplits;
     a.accumulate = 0;
     a.part_f32 = c.mode == ACC_F32 ? 1 : 0;
+    a.jl_max = jl_max;
+    a.jl_c = jl.it;
+    a.jl_waves = jl.waves;
+    a.jl_tile = jl.tile;
+    a.jl_min_j_wave = jl.min_j_wave;
+    a.jl_target_groups = jl.target_groups;
     const int64_t part_elem = a.part_f32 ? (int64_t)sizeof(float) : (int64_t)sizeof(double);
 
-    // Partial-sum scratch: S * 7 * n_i values (float64 for compensated sums,
-    // float32 for float32 sums).  When S > 1 the number of i-blocks is below
-    // target_groups, so S * n_i <= 2 * target_groups * 64 * it.
-    const int64_t bi = 64 * sh.it;
-    int64_t items, need_part;
-    if (dev_count) {
-        // Upper bound of nb * S over every block size up to n_i_cap, so that
-        // each item gets its own workgroup (dispatch order = item order, which
-        // keeps the concurrently running groups on one or two j chunks).
-        const int64_t nb_max = (n_i_max + bi - 1) / bi;
-        int64_t smax = c.n_j / ((int64_t)sh.waves * sh.min_j_wave);
-        if (smax > a.max_splits) smax = a.max_splits;
-        if (smax < 1) smax = 1;
-        const int64_t tg = sh.target_groups;
-        int64_t a1 = (tg + smax - 1) / smax;  // below this nb, S = smax
-        if (a1 > nb_max) a1 = nb_max;
-        items = a1 * smax;
-        int64_t b2 = tg + nb_max;             // nb * ceil(tg / nb) < tg + nb
-        if (b2 > nb_max * smax) b2 = nb_max * smax;
-        if (b2 > items) items = b2;
-        if (nb_max > items) items = nb_max;
-        // S * n_i <= S * nb * bi <= items * bi, and <= 2 * target_groups * bi
-        // (S > 1 only while nb < target_groups)
-        const int64_t part_rows = std::min<int64_t>(2 * tg, items) * bi;
-        need_part = part_rows * 7 * part_elem;
-        if (items > (1 << 24)) items = 1 << 24;
-    } else {
-        int64_t S = choose_splits(c.n_i, c.n_j, sh.it, sh.waves, sh.min_j_wave,
-                                  sh.target_groups, a.max_splits);
-        int64_t nb = (c.n_i + bi - 1) / bi;
-        items = nb * S;
-        need_part = S > 1 ? S * 7 * c.n_i * part_elem : 0;
-        if (items > (1 << 24)) items = 1 << 24;
+    // Grids and partial-sum scratch (S * 7 * n_i values: float32 in the
+    // float32 mode, float64 otherwise).
+    int64_t items_il = 0, items_jl = 0, need_part = 0;
+    if (use_il) {
+        const int64_t bi = 64 * il.it;
+        if (dev_count) {
+            items_il = il_items_bound(il, n_i_max, c.n_j, a.max_splits);
+            // S * n_i <= S * nb * bi <= items * bi, and <= 2 * target_groups *
+            // bi (S > 1 only while nb < target_groups)
+            const int64_t rows = std::min<int64_t>(2 * (int64_t)il.target_groups, items_il) * bi;
+            need_part = std::max(need_part, rows * 7 * part_elem);
+        } else {
+            const int64_t S = choose_splits(c.n_i, c.n_j, il.it, il.waves, il.min_j_wave,
+                                            il.target_groups, a.max_splits);
+            items_il = ((c.n_i + bi - 1) / bi) * S;
+            if (S > 1) need_part = std::max(need_part, S * 7 * c.n_i * part_elem);
+        }
     }
+    if (use_jl) {
+        if (dev_count) {
+            const int64_t cap = std::min<int64_t>(jl_max, n_i_max);
+            items_jl = jl_items_bound(jl, cap, c.n_j, a.max_splits);
+            // S * n_i <= S * nb * C = items * C
+            need_part = std::max(need_part, items_jl * jl.it * 7 * part_elem);
+        } else {
+            const int64_t S = choose_splits_jl(c.n_i, c.n_j, jl.it, jl.waves, jl.tile,
+                                               jl.min_j_wave, jl.target_groups, a.max_splits);
+            items_jl = ((c.n_i + jl.it - 1) / jl.it) * S;
+            if (S > 1) need_part = std::max(need_part, S * 7 * c.n_i * part_elem);
+        }
+    }
+    items_il = std::min<int64_t>(items_il, 1 << 24);
+    items_jl = std::min<int64_t>(items_jl, 1 << 24);
     const bool prof = ctx->prof.on && !c.part_buf;
     if (need_part > 0) {
         if (c.part_buf) {
@@ -639,12 +978,18 @@ int launch_force(nbody_ctx *ctx, const ForceCall &c) {
         }
     }
     hipEvent_t e0 = prof ? prof_mark(ctx) : nullptr;
-    hipLaunchKernelGGL(fn, dim3((unsigned)items), dim3(64 * sh.waves), 0, ctx->stream, a);
-    NB_TRY(hip_check(ctx, hipGetLastError(), "force_kernel"));
+    if (use_jl) {
+        hipLaunchKernelGGL(fjl, dim3((unsigned)items_jl), dim3(64 * jl.waves), 0, ctx->stream, a);
+        NB_TRY(hip_check(ctx, hipGetLastError(), "force_jl_kernel"));
+    }
+    if (use_il) {
+        hipLaunchKernelGGL(fil, dim3((unsigned)items_il), dim3(64 * il.waves), 0, ctx->stream, a);
+        NB_TRY(hip_check(ctx, hipGetLastError(), "force_kernel"));
+    }
     if (prof) prof_push(ctx, e0, prof_mark(ctx), 0);
     if (need_part > 0) {
         hipEvent_t r0 = prof ? prof_mark(ctx) : nullptr;
-        NB_TRY(launch_reduce_parts(ctx, a, sh.it, sh.waves, n_i_max));
+        NB_TRY(launch_reduce_parts(ctx, a, il.it, il.waves, n_i_max));
         if (prof) prof_push(ctx, r0, prof_mark(ctx), 1);
     }
     return NBODY_OK;

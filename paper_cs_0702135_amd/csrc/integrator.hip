@@ -736,6 +736,8 @@ int nbody_blockstep(nbody_ctx *ctx, const nbody_system *s, int64_t max_steps, do
     ForceCall c;
     c.mode = acc_mode(s->flags);
     c.shape = shape_for(dynamic_shape(ctx, n), c.mode);
+    c.jl_shape = shape_for(dynamic_small_shape(ctx, n, &c.jl_max), c.mode);
+    if (c.shape.rep != REP_F64) c.jl_max = 0;  // the j-lane kernel reads float64 records
     c.jrec = jr;
     c.n_j = n;
     c.pos = xp;

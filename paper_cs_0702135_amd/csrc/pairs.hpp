@@ -43,6 +43,13 @@ struct KArgs {
     int32_t max_splits;
     int32_t accumulate;  // 1: add into acc/jerk/pot instead of overwriting
     int32_t part_f32;    // 1: split partials stored as float32 (float32 sums)
+    // j-lane layout (force_jl_kernel): its split rule, and the block sizes it
+    // takes: n_i <= jl_max (the i-lane kernel takes n_i > jl_max).  Both
+    // kernels and the split reduction read the block size on the device, so
+    // the block-step driver launches both and each returns early on the
+    // other's blocks.
+    int64_t jl_max;
+    int32_t jl_c, jl_waves, jl_tile, jl_min_j_wave, jl_target_groups;
 };
 
 // Number of workgroups that share one i-block's j range.
@@ -52,6 +59,27 @@ __host__ __device__ inline int64_t choose_splits(int64_t n_i, int64_t n_j, int i
     int64_t nb = (n_i + 64 * it - 1) / (64 * it);
     if (nb < 1) nb = 1;
     int64_t s = (target_groups + nb - 1) / nb;
+    int64_t smax = n_j / ((int64_t)waves * min_j_wave);
+    if (smax > max_splits) smax = max_splits;
+    if (s > smax) s = smax;
+    if (s < 1) s = 1;
+    return s;
+}
+
+// Splits of the j range in the j-lane layout: each workgroup takes C
+// i-particles and its waves give each lane one j at a time, so a lane's
+// float32 sum has (j range per wave) / 64 terms; the split keeps that at or
+// below `tile` (as the i-lane kernel's tiles) while aiming at target_groups
+// workgroups in all.
+__host__ __device__ inline int64_t choose_splits_jl(int64_t n_i, int64_t n_j, int c, int waves,
+                                                    int tile, int min_j_wave, int target_groups,
+                                                    int max_splits) {
+    int64_t nb = (n_i + c - 1) / c;
+    if (nb < 1) nb = 1;
+    int64_t s = (target_groups + nb - 1) / nb;
+    const int64_t per_split = (int64_t)waves * 64 * tile;
+    const int64_t s_lo = (n_j + per_split - 1) / per_split;
+    if (s < s_lo) s = s_lo;
     int64_t smax = n_j / ((int64_t)waves * min_j_wave);
     if (smax > max_splits) smax = max_splits;
     if (s > smax) s = smax;

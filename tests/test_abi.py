@@ -49,7 +49,7 @@ def test_struct_layouts_match_header():
     import paper_cs_0702135_amd._lib as L
     # nbody_system: int64 n, 7 pointers, 5 doubles, uint32 flags (+ padding)
     assert ctypes.sizeof(L.NBodySystem) == 8 + 7 * 8 + 5 * 8 + 8
-    assert ctypes.sizeof(L.NBodyForceConfig) == 6 * 4
+    assert ctypes.sizeof(L.NBodyForceConfig) == 7 * 4
 
 
 def test_create_without_gpu_reports_device_error():

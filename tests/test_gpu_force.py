@@ -127,3 +127,39 @@ def test_bad_arguments_rejected():
         nb.force(dev(pos), dev(vel), dev(m), -1.0)
     with pytest.raises(nb.NBodyError):
         nb.force(dev(pos), dev(vel), dev(m), float("nan"))
+
+
+@pytest.mark.parametrize("mode", ["fp32", "ds"])
+@pytest.mark.parametrize("c,w", [(1, 1), (1, 4), (2, 2), (4, 4), (8, 1)])
+@pytest.mark.parametrize("n_i", [1, 2, 63, 64, 65, 129])
+def test_j_lane_layout(orc, n_i, c, w, mode):
+    # one j per lane, the workgroup's c i-particles shared by the wave, at
+    # ragged sizes (n = 20011: neither the splits nor the 64-j steps divide it)
+    need_gpu()
+    if mode == "ds" and c == 8:
+        pytest.skip("the compensated j-lane kernel takes at most 4 i-particles")
+    import paper_cs_0702135_amd as nb
+    n = 20011
+    pos, vel, m = plummer(n, 31)
+    act = random_active_set(n, n_i, 2000 + n_i)
+    nb.tune_clear()
+    nb.tune_set(0, 1 << 30, nb.ForceShape(0, c, w, 128, 64, 512, 1))
+    try:
+        _check(orc, pos, vel, m, (1 / 1024) ** 2, act, mode, "j-lane C=%d W=%d N=%d" % (c, w, n))
+    finally:
+        nb.tune_clear()
+
+
+@pytest.mark.parametrize("n_i", [1, 16, 64, 100])
+def test_builtin_small_block_shape_large_n(orc, n_i):
+    # the built-in shape of small blocks of a large system is the j-lane
+    # layout; against the oracle at N = 2^20
+    need_gpu()
+    import paper_cs_0702135_amd as nb
+    from workloads.plummer import CONFIGS
+    nb.tune_clear()
+    cfg = CONFIGS["plummer1m"]
+    pos, vel, m = plummer(cfg.n, cfg.seed)
+    act = random_active_set(cfg.n, n_i, 3000 + n_i)
+    for mode in ("fp32", "ds"):
+        _check(orc, pos, vel, m, cfg.eps2, act, mode, "built-in small N=2^20")

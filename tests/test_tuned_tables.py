@@ -10,9 +10,13 @@ TUNED = os.path.join(ROOT, "paper_cs_0702135_amd", "tuned")
 
 
 def _shape_ok(s):
-    return (s["rep"] in (0, 1, 2) and s["i_per_lane"] in (1, 2, 4) and s["waves"] in (1, 2, 4, 8)
-            and not (s["i_per_lane"] == 4 and s["waves"] == 8) and s["tile"] >= 1
-            and s["min_j_wave"] >= 1 and 1 <= s["target_groups"] <= (1 << 20))
+    common = s["tile"] >= 1 and s["min_j_wave"] >= 1 and 1 <= s["target_groups"] <= (1 << 20)
+    if s.get("layout", 0) == 1:
+        return (common and s["rep"] == 0 and s["i_per_lane"] in (1, 2, 4, 8)
+                and s["waves"] in (1, 2, 4))
+    return (common and s.get("layout", 0) == 0 and s["rep"] in (0, 1, 2)
+            and s["i_per_lane"] in (1, 2, 4) and s["waves"] in (1, 2, 4, 8)
+            and not (s["i_per_lane"] == 4 and s["waves"] == 8))
 
 
 def test_force_tables_hold_accepted_shapes():
@@ -25,8 +29,8 @@ def test_force_tables_hold_accepted_shapes():
         assert sizes == sorted(sizes) and len(set(sizes)) == len(sizes)
         for n_i, shape, ms in t["entries"]:
             assert n_i >= 1 and ms > 0, f
-            assert set(shape) == {"rep", "i_per_lane", "waves", "tile", "min_j_wave",
-                                  "target_groups"}, f
+            assert set(shape) - {"layout"} == {"rep", "i_per_lane", "waves", "tile",
+                                               "min_j_wave", "target_groups"}, f
             assert _shape_ok(shape), (f, n_i, shape)
 
 
