@@ -54,8 +54,8 @@ extern "C" {
 /* Relative positions and velocities are always formed in float64.  The flag
  * selects the pair arithmetic and its accumulation:
  *   NBODY_ACC_FP32  relative coordinates rounded to float32, float32 pair
- *                   terms (rsqrt on the VALU) summed in float32 over tiles
- *                   of consecutive j, the tile sums added in float64;
+ *                   terms (rsqrt on the VALU) summed in float32 over at most
+ *                   8 tiles of consecutive j, those sums added in float64;
  *   NBODY_ACC_DS    the compensated (accurate) mode.  nbody_force,
  *                   nbody_init / nbody_blockstep and nbody_shared_run
  *                   evaluate the pair terms in float64 (s^(-1/2) from the
@@ -178,6 +178,31 @@ int nbody_correct(nbody_ctx *ctx, int64_t n, int64_t n_i,
                   double dt_min, int fixed_dt, double *t, double *dt,
                   double *x, double *v, double *a, double *k);
 
+/* ---- device-counted variants ---------------------------------------------
+ * nbody_predict, nbody_force and nbody_correct with the block time and the
+ * block size read from device memory (nbody_schedule's t_next_out and
+ * n_i_out), so that schedule -> predict -> force -> correct is enqueued with
+ * no host synchronisation in between.  Same arithmetic as the host-counted
+ * entries; nbody_force_dev uses the launch shapes of the block-step driver.
+ *   t_target_dev : float64[1] device;  n_i_dev : int64[1] device.
+ *   n_i_cap      : capacity of the outputs and largest accepted block; a
+ *                  device block size above it is clamped to it and latches
+ *                  the index error (NBODY_E_INVAL at the next sync).
+ *   acc, jerk / acc_new, jerk_new : float64[3 n_i_cap], component stride
+ *                  n_i_cap;  pot : float64[n_i_cap] or NULL. */
+int nbody_predict_dev(nbody_ctx *ctx, int64_t n, const double *t_target_dev,
+                      const double *t, const double *x, const double *v,
+                      const double *a, const double *k, double *xp, double *vp);
+int nbody_force_dev(nbody_ctx *ctx, const int32_t *active_idx, const int64_t *n_i_dev,
+                    int64_t n_i_cap, const double *pos, const double *vel,
+                    const double *mass, int64_t n_j, double eps2, double *acc,
+                    double *jerk, double *pot, uint32_t flags);
+int nbody_correct_dev(nbody_ctx *ctx, int64_t n, const int64_t *n_i_dev, int64_t n_i_cap,
+                      const int32_t *active_idx, const double *xp, const double *vp,
+                      const double *acc_new, const double *jerk_new, double eta,
+                      double dt_max, double dt_min, int fixed_dt, double *t, double *dt,
+                      double *x, double *v, double *a, double *k);
+
 /* ---- initial time steps ------------------------------------------------
  * dt[i] = largest power of two <= min(eta_s |a_i|/|k_i|, dt_max) of which
  * t0 is a multiple (|k_i| = 0 gives dt_max).  A value below dt_min latches
@@ -263,7 +288,10 @@ int nbody_ensemble_run(nbody_ctx *ctx, const nbody_ensemble *e, double t_end,
  * unit and that block size), i.e. on a team of g groups
  *   T = S (step_us + [g > 1] (barrier_us + barrier_group_us g)) 1e-6
  *       + S 0.20 N^1.81 / (g group_rate),
- * and teams (at most min(max_team, 64) groups) are sized to even out T. */
+ * and teams (at most min(max_team, 64) groups) are sized to even out T.
+ * The workgroup shape (waves, j_tile, i_per_lane) must be one of the
+ * compiled ones: (4, 256, 2), (4, 256, 1), (2, 128, 2), (2, 256, 2),
+ * (4, 512, 2), (8, 512, 2). */
 typedef struct nbody_ensemble_config {
     int32_t groups_per_cu; /* 1..8 */
     int32_t max_team;      /* 1..4096 */
@@ -273,6 +301,9 @@ typedef struct nbody_ensemble_config {
     double group_rate;     /* pair interactions per second of one group */
     double steps_coef;     /* block steps per time unit = steps_coef N^steps_exp */
     double steps_exp;
+    int32_t waves;         /* waves per workgroup, sharing each j tile */
+    int32_t j_tile;        /* j particles staged in LDS per tile */
+    int32_t i_per_lane;    /* block slots per lane (1 or 2) */
 } nbody_ensemble_config;
 
 int nbody_ensemble_set(nbody_ctx *ctx, const nbody_ensemble_config *cfg);

@@ -24,6 +24,7 @@ from . import _lib as L
 
 __all__ = [
     "NBodyError", "Context", "context", "force", "force_noalloc", "predict", "schedule",
+    "schedule_async", "predict_dev", "force_dev", "correct_dev",
     "correct", "initial_dt", "energy", "System", "ACC_FP32", "ACC_DS",
     "ForceShape", "tune_set", "tune_clear", "tune_get", "profile",
     "force_adjoint", "predict_adjoint", "correct_adjoint", "ensemble_run",
@@ -224,6 +225,64 @@ def schedule(t, dt):
     return act[:k], float(tn.item())
 
 
+def schedule_async(t, dt):
+    """nbody_schedule without the host read: returns (active_idx int32 (n,),
+    n_i int64 (1,), t_next float64 (1,)) device tensors."""
+    n = t.shape[0]
+    _sca(t, n, "t"), _sca(dt, n, "dt")
+    act = torch.empty((n,), dtype=torch.int32, device=t.device)
+    n_i = torch.empty((1,), dtype=torch.int64, device=t.device)
+    tn = torch.empty((1,), dtype=torch.float64, device=t.device)
+    ctx = context(t.device)
+    ctx.check(ctx.lib.nbody_schedule(ctx.bind(), n, _ptr(t), _ptr(dt), _ptr(act), _ptr(n_i),
+                                     _ptr(tn)))
+    return act, n_i, tn
+
+
+def predict_dev(t_target, t, x, v, a, k):
+    """nbody_predict_dev: t_target is a float64 (1,) device tensor."""
+    n = t.shape[0]
+    for q, nm in ((x, "x"), (v, "v"), (a, "a"), (k, "k")):
+        _vec(q, n, nm)
+    _sca(t, n, "t")
+    xp, vp = torch.empty_like(x), torch.empty_like(v)
+    ctx = context(x.device)
+    ctx.check(ctx.lib.nbody_predict_dev(ctx.bind(), n, _ptr(t_target), _ptr(t), _ptr(x), _ptr(v),
+                                        _ptr(a), _ptr(k), _ptr(xp), _ptr(vp)))
+    return xp, vp
+
+
+def force_dev(pos, vel, mass, eps2, active_idx, n_i, n_i_cap, mode="fp32"):
+    """nbody_force_dev: the block size n_i is an int64 (1,) device tensor;
+    returns (acc (3, n_i_cap), jerk (3, n_i_cap), pot (n_i_cap,)), of which
+    the first n_i slots are set."""
+    n = mass.shape[0]
+    _vec(pos, n, "pos"), _vec(vel, n, "vel"), _sca(mass, n, "mass")
+    acc = torch.empty((3, n_i_cap), dtype=torch.float64, device=pos.device)
+    jerk = torch.empty_like(acc)
+    pot = torch.empty((n_i_cap,), dtype=torch.float64, device=pos.device)
+    ctx = context(pos.device)
+    ctx.check(ctx.lib.nbody_force_dev(ctx.bind(), _ptr(active_idx), _ptr(n_i), int(n_i_cap),
+                                      _ptr(pos), _ptr(vel), _ptr(mass), n, float(eps2),
+                                      _ptr(acc), _ptr(jerk), _ptr(pot), _mode(mode)))
+    return acc, jerk, pot
+
+
+def correct_dev(active_idx, n_i, n_i_cap, xp, vp, acc_new, jerk_new, eta, dt_max, dt_min, t,
+                dt, x, v, a, k, fixed_dt=False):
+    """nbody_correct_dev: the block size n_i is an int64 (1,) device tensor."""
+    n = t.shape[0]
+    for q, nm in ((xp, "xp"), (vp, "vp"), (x, "x"), (v, "v"), (a, "a"), (k, "k")):
+        _vec(q, n, nm)
+    _vec(acc_new, n_i_cap, "acc_new"), _vec(jerk_new, n_i_cap, "jerk_new")
+    ctx = context(x.device)
+    ctx.check(ctx.lib.nbody_correct_dev(ctx.bind(), n, _ptr(n_i), int(n_i_cap), _ptr(active_idx),
+                                        _ptr(xp), _ptr(vp), _ptr(acc_new), _ptr(jerk_new),
+                                        float(eta), float(dt_max), float(dt_min),
+                                        int(bool(fixed_dt)), _ptr(t), _ptr(dt), _ptr(x), _ptr(v),
+                                        _ptr(a), _ptr(k)))
+
+
 def correct(active_idx, xp, vp, acc_new, jerk_new, eta, dt_max, dt_min, t, dt, x, v, a, k,
             fixed_dt=False):
     """Corrector and new steps on the active particles, in place."""
@@ -347,7 +406,7 @@ def ensemble_run(pos, vel, mass, offsets, eps2, t_end, eta=0.02, eta_s=0.01, dt_
 
 def ensemble_set(groups_per_cu=None, max_team=None, step_us=None, barrier_us=None,
                  barrier_group_us=None, group_rate=None, steps_coef=None, steps_exp=None,
-                 device=None):
+                 waves=None, j_tile=None, i_per_lane=None, device=None):
     """Change the ensemble launch shape / team-planning model (None keeps)."""
     ctx = context(device)
     c = L.NBodyEnsembleConfig()
@@ -355,7 +414,8 @@ def ensemble_set(groups_per_cu=None, max_team=None, step_us=None, barrier_us=Non
     for k, v in (("groups_per_cu", groups_per_cu), ("max_team", max_team), ("step_us", step_us),
                  ("barrier_us", barrier_us), ("barrier_group_us", barrier_group_us),
                  ("group_rate", group_rate),
-                 ("steps_coef", steps_coef), ("steps_exp", steps_exp)):
+                 ("steps_coef", steps_coef), ("steps_exp", steps_exp), ("waves", waves),
+                 ("j_tile", j_tile), ("i_per_lane", i_per_lane)):
         if v is not None:
             setattr(c, k, v)
     ctx.check(ctx.lib.nbody_ensemble_set(ctx.h, ctypes.byref(c)))
@@ -399,7 +459,9 @@ def ensemble_plan(sizes, groups, t_end, config):
     cfg = L.NBodyEnsembleConfig(int(config["groups_per_cu"]), int(config["max_team"]),
                                 float(config["step_us"]), float(config["barrier_us"]),
                                 float(config["barrier_group_us"]), float(config["group_rate"]),
-                                float(config["steps_coef"]), float(config["steps_exp"]))
+                                float(config["steps_coef"]), float(config["steps_exp"]),
+                                int(config.get("waves", 4)), int(config.get("j_tile", 256)),
+                                int(config.get("i_per_lane", 2)))
     team_of = _np.empty(nc, dtype=_np.int32)
     team_size = _np.empty(nc, dtype=_np.int32)
     secs = _np.empty(nc, dtype=_np.float64)

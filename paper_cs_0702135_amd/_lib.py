@@ -58,7 +58,8 @@ class NBodyEnsembleConfig(ctypes.Structure):
     """Mirror of ``nbody_ensemble_config`` in include/nbody.h."""
     _fields_ = [("groups_per_cu", I32), ("max_team", I32), ("step_us", D),
                 ("barrier_us", D), ("barrier_group_us", D), ("group_rate", D),
-                ("steps_coef", D), ("steps_exp", D)]
+                ("steps_coef", D), ("steps_exp", D), ("waves", I32), ("j_tile", I32),
+                ("i_per_lane", I32)]
 
 
 # name -> (restype, argtypes); every symbol include/nbody.h declares
@@ -76,6 +77,10 @@ SIGNATURES = {
     "nbody_correct": (INT, [P, I64, I64, P, P, P, P, P, D, D, D, INT, P, P, P, P,
                             P, P]),
     "nbody_initial_dt": (INT, [P, I64, D, P, P, D, D, D, P]),
+    "nbody_predict_dev": (INT, [P, I64, P, P, P, P, P, P, P, P]),
+    "nbody_force_dev": (INT, [P, P, P, I64, P, P, P, I64, D, P, P, P, U32]),
+    "nbody_correct_dev": (INT, [P, I64, P, I64, P, P, P, P, P, D, D, D, INT, P, P, P, P,
+                                P, P]),
     "nbody_energy": (INT, [P, I64, P, P, P, D, P]),
     "nbody_init": (INT, [P, ctypes.POINTER(NBodySystem), D]),
     "nbody_blockstep": (INT, [P, ctypes.POINTER(NBodySystem), I64, D,

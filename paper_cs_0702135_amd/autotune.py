@@ -233,31 +233,47 @@ def _fit_model(rows, cfg, t_end):
     return new
 
 
-def calibrate_ensemble(mode="fp32", t_end=1.0 / 16, dt_max=1.0 / 16, log=None, rounds=3):
-    """Fit the team-planning model by running a representative ensemble,
-    refitting on its per-cluster times and re-planning; keep the fastest."""
+ENS_FIELDS = ("groups_per_cu", "max_team", "step_us", "barrier_us", "barrier_group_us",
+              "group_rate", "steps_coef", "steps_exp", "waves", "j_tile", "i_per_lane")
+
+# Workgroup shapes of the ensemble kernel the library compiles:
+# (waves per group, j records per LDS tile, block slots per lane).
+ENS_SHAPES = ((4, 256, 2), (4, 256, 1), (2, 128, 2), (2, 256, 2), (4, 512, 2), (8, 512, 2))
+
+
+def calibrate_ensemble(mode="fp32", t_end=1.0 / 16, dt_max=1.0 / 16, log=None, rounds=3,
+                       shapes=ENS_SHAPES):
+    """Choose the ensemble's workgroup shape and fit its team-planning model:
+    for every compiled shape at 2 and 3 waves per SIMD, run a representative
+    ensemble, refit the model on its per-cluster times, re-plan and run
+    again; keep the fastest launch's shape and model."""
     from . import ensemble_get, ensemble_set
     saved = ensemble_get()
     inp = _ens_mixed_inputs()
     best = None
     try:
-        for gpc in (2, 3):
-            cfg = dict(saved, groups_per_cu=gpc)
-            for k in range(rounds):
-                ensemble_set(**cfg)
-                secs, rows = _ens_mixed_run(inp, mode, t_end, dt_max)
-                if log:
-                    log("ensemble calibration gpc=%d round %d: %.4f s" % (gpc, k, secs))
-                if best is None or secs < best[1]:
-                    best = (dict(cfg), secs)
-                cfg = _fit_model(rows, cfg, t_end)
+        for waves, tile, ipl in shapes:
+            for wps in (2, 3):  # waves per SIMD
+                gpc = max(1, wps * 4 // waves)
+                cfg = dict(saved, groups_per_cu=gpc, waves=waves, j_tile=tile, i_per_lane=ipl)
+                for k in range(rounds):
+                    ensemble_set(**cfg)
+                    secs, rows = _ens_mixed_run(inp, mode, t_end, dt_max)
+                    if log:
+                        log("ensemble calibration shape (%d, %d, %d) gpc=%d round %d: %.4f s"
+                            % (waves, tile, ipl, gpc, k, secs))
+                    if best is None or secs < best[1]:
+                        best = (dict(cfg), secs)
+                    cfg = _fit_model(rows, cfg, t_end)
         cfg = best[0]
         if log:
-            log("ensemble model: step %.1f us, barrier %.1f + %.2f g us, group rate %.3e /s, "
-                "steps %.1f N^%.3f per time unit, %d groups per CU (%.4f s)"
-                % (cfg["step_us"], cfg["barrier_us"], cfg["barrier_group_us"],
-                   cfg["group_rate"], cfg["steps_coef"], cfg["steps_exp"],
-                   cfg["groups_per_cu"], best[1]))
+            log("ensemble model: shape (%d waves, tile %d, %d per lane), step %.1f us, barrier "
+                "%.1f + %.2f g us, group rate %.3e /s, steps %.1f N^%.3f per time unit, "
+                "%d groups per CU (%.4f s)"
+                % (cfg["waves"], cfg["j_tile"], cfg["i_per_lane"], cfg["step_us"],
+                   cfg["barrier_us"], cfg["barrier_group_us"], cfg["group_rate"],
+                   cfg["steps_coef"], cfg["steps_exp"], cfg["groups_per_cu"], best[1]))
+        cfg["calibration_seconds"] = best[1]
         return cfg
     finally:
         ensemble_set(**saved)
@@ -275,5 +291,5 @@ def load_or_calibrate_ensemble(mode="fp32", log=None):
         os.makedirs(CACHE_DIR, exist_ok=True)
         with open(p, "w") as f:
             json.dump(cfg, f, indent=1)
-    ensemble_set(**cfg)
+    ensemble_set(**{k: v for k, v in cfg.items() if k in ENS_FIELDS})
     return cfg

@@ -84,7 +84,7 @@ struct nbody_ctx {
     size_t ens_bytes = 0;
     void *static_scratch = nullptr;  // this device's copy of the static scratch
     int static_scratch_rc = 0;       // hipGetSymbolAddress status (hipError_t)
-    nbody_ensemble_config ens_cfg = {2, 64, 30.0, 15.0, 0.5, 2.0e9, 247.0, 0.35};
+    nbody_ensemble_config ens_cfg = {2, 64, 30.0, 15.0, 0.5, 2.0e9, 247.0, 0.35, 4, 256, 2};
     int ens_last_grid = 0;
     int ens_last_teams = 0;
     std::vector<double> ens_last_seconds;  // per cluster, last ensemble launch
@@ -112,6 +112,12 @@ void prof_push(nbody_ctx *ctx, hipEvent_t a, hipEvent_t b, int kind);
 void prof_resolve(nbody_ctx *ctx);
 
 ForceShape pick_shape(const nbody_ctx *ctx, int64_t n_i, int64_t n_j);
+// Compiled launch shapes of the ensemble kernel (ensemble.hip): the one with
+// w waves per group, j tiles of `tile` records and `it` slots per lane, or
+// null.
+struct EnsVariant;
+const EnsVariant *find_variant(int w, int tile, int it);
+
 // Pair-arithmetic mode (ACC_* in pairs.hpp) of the NBODY_ACC_* flags, and
 // the shape a mode runs in: float64 pair terms need float64 records and take
 // at most two i-particles per lane.

@@ -265,6 +265,10 @@ int nbody_ensemble_set(nbody_ctx *ctx, const nbody_ensemble_config *cfg) {
         std::isinf(cfg->group_rate) || !(cfg->steps_coef > 0) || !(cfg->steps_exp >= 0) ||
         !(cfg->steps_exp < 3) || std::isinf(cfg->steps_coef))
         return fail(ctx, NBODY_E_INVAL, "nbody_ensemble_set: bad values");
+    if (!find_variant(cfg->waves, cfg->j_tile, cfg->i_per_lane))
+        return fail(ctx, NBODY_E_INVAL,
+                    "nbody_ensemble_set: no compiled shape with %d waves, tile %d, %d per lane",
+                    cfg->waves, cfg->j_tile, cfg->i_per_lane);
     ctx->ens_cfg = *cfg;
     return NBODY_OK;
 }

@@ -27,9 +27,10 @@
 //
 // The j particles of a pair-sum pass are staged through LDS in tiles (the
 // state is rewritten during this launch, so it cannot be read through the
-// scalar cache as in the standalone kernel); the four waves of a group
-// share one tile, each taking a quarter of it for the group's 64 * EIT
-// block slots, and their sums are combined in float64 in wave order.
+// scalar cache as in the standalone kernel); the W waves of a group share
+// one tile, each taking a W-th of it for the group's 64 * IT block slots,
+// and their sums are combined in float64 in wave order.  W, the tile and IT
+// are compile-time shapes (ESh) among which the autotuner chooses.
 #include <algorithm>
 #include <cmath>
 #include <numeric>
@@ -41,9 +42,15 @@
 
 namespace nb {
 
-constexpr int EW = 4;            // waves per group
-constexpr int ETH = 64 * EW;     // threads per group
-constexpr int ETILE = 256;       // j records per LDS tile
+// Launch shape of the ensemble kernel.
+template <int W_, int TILE_, int IT_>
+struct ESh {
+    static constexpr int W = W_;        // waves per group (2, 4 or 8)
+    static constexpr int TH = 64 * W_;  // threads per group
+    static constexpr int TILE = TILE_;  // j records per LDS tile (a multiple of 64 W)
+    static constexpr int IT = IT_;      // most i-slots per lane (1 or 2)
+    static_assert(W_ >= 2 && TILE_ % (64 * W_) == 0 && (IT_ == 1 || IT_ == 2), "shape");
+};
 constexpr int EMAXSPLIT = 64;    // largest j split of a team's pair pass
 
 struct EnsCluster {
@@ -211,6 +218,7 @@ __device__ __forceinline__ void raw_state(const Raw &r, double tn, double px[3],
 }
 
 // Minimum over the group (every thread gets it).
+template <class Sh>
 __device__ __forceinline__ double group_min(double v, double *smin) {
 #pragma unroll
     for (int o = 32; o >= 1; o >>= 1) v = fmin(v, __shfl_xor(v, o, 64));
@@ -219,7 +227,7 @@ __device__ __forceinline__ double group_min(double v, double *smin) {
     __syncthreads();
     double r = smin[0];
 #pragma unroll
-    for (int w = 1; w < EW; ++w) r = fmin(r, smin[w]);
+    for (int w = 1; w < Sh::W; ++w) r = fmin(r, smin[w]);
     return r;
 }
 
@@ -235,13 +243,12 @@ __device__ __forceinline__ double group_min(double v, double *smin) {
 // it is masked by index only for eps2 < 1e-12.  (Holding the next j tile
 // in registers while the current one is summed would cost the third group
 // per CU its registers; the co-resident groups hide the tile loads.)
-constexpr int EIT = 2;          // most i-slots per lane
 constexpr float EMASK = 1e-12f;  // below this eps2 the self pair is masked
 
-template <bool DS, bool PRED, int NI, int L>
+template <class Sh, bool DS, bool PRED, int NI, int L>
 __device__ void ens_pair_item(const EnsArgs &A, int64_t base, float eps2, double tn,
                               const Block &B, int n_i, int slot0, int j0, int j1, TileRec *tile,
-                              double (*red)[6 * EIT][64], double (&tot)[EIT][6]) {
+                              double (*red)[6 * Sh::IT][64], double (&tot)[Sh::IT][6]) {
     constexpr int SPL = 64 / L;
     const int tid = threadIdx.x;
     const int lane = tid & 63;
@@ -280,12 +287,13 @@ __device__ void ens_pair_item(const EnsArgs &A, int64_t base, float eps2, double
     for (int t = 0; t < NI; ++t)
 #pragma unroll
         for (int c = 0; c < 6; ++c) sh[t][c] = sl[t][c] = 0.0f;
-    for (int jt = j0; jt < j1; jt += ETILE) {
-        const int cnt = min(ETILE, j1 - jt);
+    constexpr int PER = Sh::TILE / Sh::W;  // tile records per wave
+    for (int jt = j0; jt < j1; jt += Sh::TILE) {
+        const int cnt = min(Sh::TILE, j1 - jt);
         __syncthreads();
-        if (tid < cnt) {
+        for (int q = tid; q < cnt; q += Sh::TH) {
             Raw nxt;
-            load_raw<PRED>(A, base + jt + tid, nxt);
+            load_raw<PRED>(A, base + jt + q, nxt);
             double px[3], pv[3];
             raw_state<PRED>(nxt, tn, px, pv);
             TileRec R;
@@ -296,10 +304,10 @@ __device__ void ens_pair_item(const EnsArgs &A, int64_t base, float eps2, double
             R.v = pv[1];
             R.w = pv[2];
             R.m = nxt.m;
-            tile[tid] = R;
+            tile[q] = R;
         }
         __syncthreads();
-        const int r0 = wave * 64, r1 = min(cnt, r0 + 64);
+        const int r0 = wave * PER, r1 = min(cnt, r0 + PER);
         float in[NI][6];
 #pragma unroll
         for (int t = 0; t < NI; ++t)
@@ -361,7 +369,7 @@ __device__ void ens_pair_item(const EnsArgs &A, int64_t base, float eps2, double
             for (int c = 0; c < 6; ++c) red[wave - 1][t * 6 + c][lane] = tot[t][c];
     __syncthreads();
     if (wave == 0)
-        for (int w = 1; w < EW; ++w)
+        for (int w = 1; w < Sh::W; ++w)
 #pragma unroll
             for (int t = 0; t < NI; ++t)
 #pragma unroll
@@ -369,10 +377,15 @@ __device__ void ens_pair_item(const EnsArgs &A, int64_t base, float eps2, double
 }
 
 // Width of the item of a block that starts at slot0: 128 slots (two per
-// lane) while more than 64 remain, else the narrowest of 64, 32, 16, 8
-// that holds the rest (the last three split j over 2, 4, 8 lanes).
+// lane, with IT = 2) while more than 64 remain, else the narrowest of 64,
+// 32, 16, 8 that holds the rest (the last three split j over 2, 4, 8 lanes).
+template <int IT>
 __device__ __forceinline__ int item_width(int rem, bool narrow) {
-    const int w = rem > 64 ? 128 : rem > 32 ? 64 : rem > 16 ? 32 : rem > 8 ? 16 : 8;
+    const int w = (IT == 2 && rem > 64) ? 128
+                  : rem > 32             ? 64
+                  : rem > 16             ? 32
+                  : rem > 8              ? 16
+                                         : 8;
     return narrow ? w : max(w, 64);
 }
 
@@ -380,15 +393,15 @@ __device__ __forceinline__ int item_width(int rem, bool narrow) {
 // spread over the team: results in anew/knew (slot-major, component stride
 // n_max); returns false on abort.  Items are 128 slots apart; the last one
 // is as narrow as its remainder allows.
-template <bool DS, bool PRED>
+template <class Sh, bool DS, bool PRED>
 __device__ bool ens_pairs(const EnsArgs &A, int64_t base, int n, float eps2, double tn,
                           const Block &B, int n_i, int g, int rank, int s_max, int n_max,
                           double *anew, double *knew, double *part, uint32_t *bar,
-                          uint32_t &epoch, TileRec *tile, double (*red)[6 * EIT][64]) {
+                          uint32_t &epoch, TileRec *tile, double (*red)[6 * Sh::IT][64]) {
     if (n_i < 1) return team_barrier(bar, g, rank, epoch, A.abort, A.spin_limit);
-    const int64_t nb = (n_i + 64 * EIT - 1) / (64 * EIT);
+    const int64_t nb = (n_i + 64 * Sh::IT - 1) / (64 * Sh::IT);
     int64_t S = (g + nb - 1) / nb;  // about one item per group
-    int64_t smax = max(1, n / ETILE);
+    int64_t smax = max(1, n / Sh::TILE);
     if (smax > s_max) smax = s_max;
     if (S > smax) S = smax;
     if (S < 1) S = 1;
@@ -398,28 +411,33 @@ __device__ bool ens_pairs(const EnsArgs &A, int64_t base, int n, float eps2, dou
     for (int64_t it = rank; it < items; it += g) {
         const int64_t ib = it % nb, sp = it / nb;
         const int j0 = (int)(sp * jchunk), j1 = min(n, j0 + jchunk);
-        const int slot0 = (int)(ib * 64 * EIT);
-        const int w = item_width(n_i - slot0, PRED);
-        double tot[EIT][6];
+        const int slot0 = (int)(ib * 64 * Sh::IT);
+        const int w = item_width<Sh::IT>(n_i - slot0, PRED);
+        double tot[Sh::IT][6];
         int ni = 1, L = 1;
-        if (w == 128) {
-            ens_pair_item<DS, PRED, 2, 1>(A, base, eps2, tn, B, n_i, slot0, j0, j1, tile, red, tot);
+        if (Sh::IT == 2 && w == 128) {
+            ens_pair_item<Sh, DS, PRED, Sh::IT, 1>(A, base, eps2, tn, B, n_i, slot0, j0, j1,
+                                                   tile, red, tot);
             ni = 2;
         } else if (w == 64) {
-            ens_pair_item<DS, PRED, 1, 1>(A, base, eps2, tn, B, n_i, slot0, j0, j1, tile, red, tot);
+            ens_pair_item<Sh, DS, PRED, 1, 1>(A, base, eps2, tn, B, n_i, slot0, j0, j1, tile, red,
+                                              tot);
         } else if (PRED && w == 32) {
-            ens_pair_item<DS, PRED, 1, 2>(A, base, eps2, tn, B, n_i, slot0, j0, j1, tile, red, tot);
+            ens_pair_item<Sh, DS, PRED, 1, 2>(A, base, eps2, tn, B, n_i, slot0, j0, j1, tile, red,
+                                              tot);
             L = 2;
         } else if (PRED && w == 16) {
-            ens_pair_item<DS, PRED, 1, 4>(A, base, eps2, tn, B, n_i, slot0, j0, j1, tile, red, tot);
+            ens_pair_item<Sh, DS, PRED, 1, 4>(A, base, eps2, tn, B, n_i, slot0, j0, j1, tile, red,
+                                              tot);
             L = 4;
         } else if (PRED) {
-            ens_pair_item<DS, PRED, 1, 8>(A, base, eps2, tn, B, n_i, slot0, j0, j1, tile, red, tot);
+            ens_pair_item<Sh, DS, PRED, 1, 8>(A, base, eps2, tn, B, n_i, slot0, j0, j1, tile, red,
+                                              tot);
             L = 8;
         }
         if ((threadIdx.x >> 6) == 0 && lane % L == 0) {
 #pragma unroll
-            for (int t = 0; t < EIT; ++t) {
+            for (int t = 0; t < Sh::IT; ++t) {
                 const int slot = slot0 + t * (64 / L) + lane / L;
                 if (t >= ni || slot >= n_i) continue;
                 if (S == 1) {
@@ -438,7 +456,8 @@ __device__ bool ens_pairs(const EnsArgs &A, int64_t base, int n, float eps2, dou
     if (S > 1) {
         if (!team_barrier(bar, g, rank, epoch, A.abort, A.spin_limit)) return false;
         const int64_t total = 6 * (int64_t)n_i;
-        for (int64_t e = (int64_t)rank * ETH + threadIdx.x; e < total; e += (int64_t)g * ETH) {
+        for (int64_t e = (int64_t)rank * Sh::TH + threadIdx.x; e < total;
+             e += (int64_t)g * Sh::TH) {
             const int c = (int)(e / n_i), s = (int)(e - (int64_t)c * n_i);
             double acc = 0.0;
             for (int64_t p = 0; p < S; ++p) acc += part[(p * 6 + c) * n_max + s];
@@ -471,10 +490,12 @@ __device__ __forceinline__ double load_relaxed(const double *p) {
 // block time needs no pass of its own.  The per-group minima are
 // double-buffered by step parity: a group may publish the next step's
 // values while a slower one still reads this step's.
-template <bool DS>
-__global__ __launch_bounds__(ETH, 3) void ensemble_kernel(const EnsArgs A) {
-    __shared__ TileRec tile[ETILE];
-    __shared__ double red[EW - 1][6 * EIT][64];
+template <class Sh, bool DS>
+__global__ __launch_bounds__(Sh::TH, 3) void ensemble_kernel(const EnsArgs A) {
+    constexpr int ETH = Sh::TH;
+    constexpr int EW = Sh::W;
+    __shared__ TileRec tile[Sh::TILE];
+    __shared__ double red[EW - 1][6 * Sh::IT][64];
     __shared__ double smin[EW];
     __shared__ int scount[4 * EW];
     __shared__ int spre[65];
@@ -511,8 +532,8 @@ __global__ __launch_bounds__(ETH, 3) void ensemble_kernel(const EnsArgs A) {
 
         // ---- initialisation: pair sums of every particle, initial steps
         const Block whole{nullptr, spre, g, per, n};
-        if (!ens_pairs<DS, false>(A, base, n, eps2, 0.0, whole, n, g, rank, T.s_max, n_max,
-                                  anew, knew, part, bar, epoch, tile, red))
+        if (!ens_pairs<Sh, DS, false>(A, base, n, eps2, 0.0, whole, n, g, rank, T.s_max, n_max,
+                                      anew, knew, part, bar, epoch, tile, red))
             return;
         double mn = INFINITY;
         for (int i = p0 + tid; i < p1; i += ETH) {
@@ -530,7 +551,7 @@ __global__ __launch_bounds__(ETH, 3) void ensemble_kernel(const EnsArgs A) {
             mn = fmin(mn, 0.0 + d);
             if (st) atomicOr(A.status, st);
         }
-        mn = group_min(mn, smin);
+        mn = group_min<Sh>(mn, smin);
         if (tid == 0) {
             store_relaxed(&pm[rank], INFINITY);
             store_relaxed(&pm[g + rank], mn);
@@ -585,7 +606,7 @@ __global__ __launch_bounds__(ETH, 3) void ensemble_kernel(const EnsArgs A) {
                 }
                 __syncthreads();
             }
-            rmin = group_min(rmin, smin);
+            rmin = group_min<Sh>(rmin, smin);
             if (tid == 0) {
                 store_relaxed(&pm[(2 * nx) * g + rank], rmin);
                 __hip_atomic_store(&pcnt[rank], local, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -608,8 +629,8 @@ __global__ __launch_bounds__(ETH, 3) void ensemble_kernel(const EnsArgs A) {
             const Block blk{act, spre, g, per, n};
 
             // ---- B: pair sums of the block at the predicted state
-            if (!ens_pairs<DS, true>(A, base, n, eps2, tn, blk, n_i, g, rank, T.s_max, n_max,
-                                     anew, knew, part, bar, epoch, tile, red))
+            if (!ens_pairs<Sh, DS, true>(A, base, n, eps2, tn, blk, n_i, g, rank, T.s_max, n_max,
+                                         anew, knew, part, bar, epoch, tile, red))
                 return;
 
             // ---- C: correct the slice's members; minimum of the new t + dt
@@ -633,7 +654,7 @@ __global__ __launch_bounds__(ETH, 3) void ensemble_kernel(const EnsArgs A) {
                 if (st) atomicOr(A.status, st);
                 nmin = fmin(nmin, A.t[q] + A.dt[q]);
             }
-            nmin = group_min(nmin, smin);
+            nmin = group_min<Sh>(nmin, smin);
             if (tid == 0) store_relaxed(&pm[(2 * nx + 1) * g + rank], nmin);
             my_steps += 1;
             my_inter += (int64_t)n_i * n;
@@ -661,6 +682,30 @@ __global__ void ens_clear_kernel(uint32_t *bars, int64_t nbars, int64_t *steps, 
         clock[2 * i] = clock[2 * i + 1] = 0;
     }
     if (i < 2) flags[i] = 0;
+}
+
+// ---- compiled launch shapes ------------------------------------------------
+struct EnsVariant {
+    int w, tile, it, th;
+    const void *fn[2];  // float32 sums, compensated sums
+};
+
+template <int W, int TILE, int IT>
+static EnsVariant ens_variant() {
+    typedef ESh<W, TILE, IT> S;
+    return EnsVariant{W, TILE, IT, S::TH,
+                      {(const void *)ensemble_kernel<S, false>,
+                       (const void *)ensemble_kernel<S, true>}};
+}
+
+const EnsVariant *find_variant(int w, int tile, int it) {
+    static const EnsVariant v[] = {
+        ens_variant<4, 256, 2>(), ens_variant<4, 256, 1>(), ens_variant<2, 128, 2>(),
+        ens_variant<2, 256, 2>(), ens_variant<4, 512, 2>(), ens_variant<8, 512, 2>(),
+    };
+    for (const EnsVariant &x : v)
+        if (x.w == w && x.tile == tile && x.it == it) return &x;
+    return nullptr;
 }
 
 // ---- host-side team planning ----------------------------------------------
@@ -816,7 +861,11 @@ extern "C" int nbody_ensemble_run(nbody_ctx *ctx, const nbody_ensemble *e, doubl
     NB_TRY(activate(ctx));
 
     const bool ds = (e->flags & NBODY_ACC_DS) != 0;
-    const void *kfn = ds ? (const void *)ensemble_kernel<true> : (const void *)ensemble_kernel<false>;
+    const EnsVariant *var = find_variant(ctx->ens_cfg.waves, ctx->ens_cfg.j_tile,
+                                         ctx->ens_cfg.i_per_lane);
+    if (!var) return fail(ctx, NBODY_E_INVAL, "ensemble: shape not compiled");
+    const void *kfn = var->fn[ds ? 1 : 0];
+    const int ETH = var->th;
     int occ = 0;
     NB_TRY(hip_check(ctx, hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, kfn, ETH, 0),
                      "occupancy"));

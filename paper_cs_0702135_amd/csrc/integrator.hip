@@ -22,6 +22,7 @@ __device__ __forceinline__ void latch(StepInfo *info, int32_t bits) {
 
 // ---------------------------------------------------------------- predictor
 __global__ void predict_kernel(int64_t n, double t_target, const StepInfo *__restrict__ info,
+                               const double *__restrict__ t_target_dev,
                                const double *__restrict__ t, const double *__restrict__ x,
                                const double *__restrict__ v, const double *__restrict__ a,
                                const double *__restrict__ k, double *__restrict__ xp,
@@ -29,7 +30,7 @@ __global__ void predict_kernel(int64_t n, double t_target, const StepInfo *__res
                                JRec *__restrict__ jrec, int rep) {
 #pragma clang fp contract(off)
     if (info && info->done) return;
-    const double tt = info ? info->t_next : t_target;
+    const double tt = info ? info->t_next : (t_target_dev ? *t_target_dev : t_target);
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
          i += (int64_t)gridDim.x * blockDim.x) {
         double px[3], pv[3];
@@ -460,7 +461,8 @@ __global__ void set_info_kernel(StepInfo *info, double t_end, int reset_counters
 }
 
 // ---------------------------------------------------------------- corrector
-__global__ void correct_kernel(int64_t n, int64_t n_i_arg, const StepInfo *__restrict__ cinfo,
+__global__ void correct_kernel(int64_t n, int64_t n_i_arg, const int64_t *__restrict__ n_i_dev,
+                               const StepInfo *__restrict__ cinfo,
                                StepInfo *__restrict__ sinfo, const int32_t *__restrict__ active,
                                const double *__restrict__ xp, const double *__restrict__ vp,
                                const double *__restrict__ acc_new,
@@ -476,7 +478,15 @@ __global__ void correct_kernel(int64_t n, int64_t n_i_arg, const StepInfo *__res
     // block (infinity for blocks without one), for the next step's t_next;
     // nothing once the run is done (no block was scheduled)
     if (mins && cinfo->done) return;
-    const int64_t n_i = cinfo ? cinfo->n_i : n_i_arg;
+    int64_t n_i = cinfo ? cinfo->n_i : n_i_arg;
+    if (n_i_dev) {
+        // device-counted block of at most n_i_arg slots
+        n_i = *n_i_dev;
+        if (n_i > n_i_arg) {
+            if (blockIdx.x == 0 && threadIdx.x == 0) latch(sinfo, ST_INDEX);
+            n_i = n_i_arg;
+        }
+    }
     const int64_t sn = stride_new > 0 ? stride_new : n_i;
     double m = INFINITY;
     for (int64_t s = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; s < n_i;
@@ -604,7 +614,7 @@ int nbody_predict(nbody_ctx *ctx, int64_t n, double t_target, const double *t, c
         return fail(ctx, NBODY_E_INVAL, "nbody_predict: null array");
     NB_TRY(activate(ctx));
     predict_kernel<<<grid_for(n, 256, 16 * ctx->cus), 256, 0, ctx->stream>>>(
-        n, t_target, nullptr, t, x, v, a, k, xp, vp, nullptr, nullptr, 0);
+        n, t_target, nullptr, nullptr, t, x, v, a, k, xp, vp, nullptr, nullptr, 0);
     return hip_check(ctx, hipGetLastError(), "predict_kernel");
 }
 
@@ -632,8 +642,41 @@ int nbody_correct(nbody_ctx *ctx, int64_t n, int64_t n_i, const int32_t *active_
         return fail(ctx, NBODY_E_INVAL, "nbody_correct: null array");
     NB_TRY(activate(ctx));
     correct_kernel<<<grid_for(n_i, 256, 16 * ctx->cus), 256, 0, ctx->stream>>>(
-        n, n_i, nullptr, ctx->info, active_idx, xp, vp, acc_new, jerk_new, n_i, eta, dt_max,
+        n, n_i, nullptr, nullptr, ctx->info, active_idx, xp, vp, acc_new, jerk_new, n_i, eta, dt_max,
         dt_min, fixed_dt, t, dt, x, v, a, k, nullptr);
+    return hip_check(ctx, hipGetLastError(), "correct_kernel");
+}
+
+int nbody_predict_dev(nbody_ctx *ctx, int64_t n, const double *t_target_dev, const double *t,
+                      const double *x, const double *v, const double *a, const double *k,
+                      double *xp, double *vp) {
+    if (!ctx) return NBODY_E_INVAL;
+    if (n < 0) return fail(ctx, NBODY_E_INVAL, "nbody_predict_dev: bad args");
+    if (n == 0) return NBODY_OK;
+    if (!t_target_dev || !t || !x || !v || !a || !k || !xp || !vp)
+        return fail(ctx, NBODY_E_INVAL, "nbody_predict_dev: null array");
+    NB_TRY(activate(ctx));
+    predict_kernel<<<grid_for(n, 256, 16 * ctx->cus), 256, 0, ctx->stream>>>(
+        n, 0.0, nullptr, t_target_dev, t, x, v, a, k, xp, vp, nullptr, nullptr, 0);
+    return hip_check(ctx, hipGetLastError(), "predict_kernel");
+}
+
+int nbody_correct_dev(nbody_ctx *ctx, int64_t n, const int64_t *n_i_dev, int64_t n_i_cap,
+                      const int32_t *active_idx, const double *xp, const double *vp,
+                      const double *acc_new, const double *jerk_new, double eta, double dt_max,
+                      double dt_min, int fixed_dt, double *t, double *dt, double *x, double *v,
+                      double *a, double *k) {
+    if (!ctx) return NBODY_E_INVAL;
+    if (n < 1 || n_i_cap < 0 || (active_idx == nullptr && n_i_cap > n) || !(dt_min > 0) ||
+        !(dt_max >= dt_min) || !(eta > 0 || fixed_dt))
+        return fail(ctx, NBODY_E_INVAL, "nbody_correct_dev: bad args");
+    if (n_i_cap == 0) return NBODY_OK;
+    if (!n_i_dev || !xp || !vp || !acc_new || !jerk_new || !t || !dt || !x || !v || !a || !k)
+        return fail(ctx, NBODY_E_INVAL, "nbody_correct_dev: null array");
+    NB_TRY(activate(ctx));
+    correct_kernel<<<grid_for(n_i_cap, 256, 16 * ctx->cus), 256, 0, ctx->stream>>>(
+        n, n_i_cap, n_i_dev, nullptr, ctx->info, active_idx, xp, vp, acc_new, jerk_new, n_i_cap,
+        eta, dt_max, dt_min, fixed_dt, t, dt, x, v, a, k, nullptr);
     return hip_check(ctx, hipGetLastError(), "correct_kernel");
 }
 
@@ -795,7 +838,7 @@ int nbody_blockstep(nbody_ctx *ctx, const nbody_system *s, int64_t max_steps, do
             }
             NB_TRY(launch_force(ctx, c));
             correct_kernel<<<small ? gp : gc, 256, 0, ctx->stream>>>(
-                n, 0, ctx->info, ctx->info, act, xp, vp, an, kn, n, s->eta, s->dt_max, s->dt_min,
+                n, 0, nullptr, ctx->info, ctx->info, act, xp, vp, an, kn, n, s->eta, s->dt_max, s->dt_min,
                 (s->flags & NBODY_FIXED_DT) ? 1 : 0, s->t, s->dt, s->x, s->v, s->a, s->k,
                 small ? nullptr : cmin);
             NB_TRY(hip_check(ctx, hipGetLastError(), "correct_kernel"));

@@ -13,9 +13,9 @@ constexpr int kMaxSplits = 1024;  // largest j split across workgroups
 
 // Arithmetic and accumulation of the pair terms:
 //   ACC_F32  (NBODY_ACC_FP32) float32 pair terms summed in float32 over a
-//            tile of consecutive j; each tile sum is added to a float64
-//            total, so no float32 sum spans more than one tile whatever the
-//            launch shape;
+//            tile of consecutive j; the tile sums of a few tiles are added
+//            in float32, then to a float64 total, so no float32 sum spans
+//            more than a fixed number of j whatever the launch shape;
 //   ACC_F64  (NBODY_ACC_DS) float64 pair terms and float64 sums (float64
 //            records only).
 enum { ACC_F32 = 0, ACC_F64 = 1 };
@@ -51,6 +51,15 @@ struct KArgs {
     int64_t jl_max;
     int32_t jl_c, jl_waves, jl_tile, jl_min_j_wave, jl_target_groups;
 };
+
+// Active-block size of a launch: read on the device when n_i_dev is set
+// (then a.n_i is the capacity of the outputs and larger values are clamped
+// to it), else a.n_i.
+__device__ __forceinline__ int64_t block_size(const KArgs &a) {
+    if (!a.n_i_dev) return a.n_i;
+    const int64_t v = *a.n_i_dev;
+    return v < a.n_i ? v : a.n_i;
+}
 
 // Number of workgroups that share one i-block's j range.
 __host__ __device__ inline int64_t choose_splits(int64_t n_i, int64_t n_j, int it, int waves,

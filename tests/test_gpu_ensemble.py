@@ -108,3 +108,79 @@ def test_full_ensemble_workload(orc):
             % (c, sizes[c], gs, rs, dx, drift))
         assert abs(gs - rs) <= max(2, 0.03 * rs)
         assert dx < 1e-6
+
+
+@pytest.mark.parametrize("shape", [(4, 256, 1), (2, 128, 2), (2, 256, 2), (4, 512, 2),
+                                   (8, 512, 2)])
+def test_every_compiled_shape(orc, shape):
+    # the workgroup shapes the autotuner chooses among integrate like the
+    # default one: same steps as the oracle's runs, final positions within
+    # 1e-6 of the oracle's and of the default shape's (only the order of the
+    # float64 combination of wave and split sums differs)
+    need_gpu()
+    import paper_cs_0702135_amd as nb
+    saved = nb.ensemble_get()
+    waves, tile, ipl = shape
+    sizes = [64, 100, 300, 1024, 2000]
+    seeds = [21, 22, 23, 24, 25]
+    try:
+        for mode in ("fp32", "ds"):
+            nb.ensemble_set(waves=4, j_tile=256, i_per_lane=2, groups_per_cu=3)
+            ref = host(_run(sizes, seeds, mode=mode)[-1]["x"])
+            nb.ensemble_set(waves=waves, j_tile=tile, i_per_lane=ipl,
+                            groups_per_cu=max(1, 12 // waves))
+            pos, vel, m, off, eps2, out = _run(sizes, seeds, mode=mode)
+            d_default = np.abs(host(out["x"]) - ref).max()
+            say("shape %r %s: max |x - x(default shape)| %.2e" % (shape, mode, d_default))
+            assert d_default < 1e-6
+            for c in range(len(sizes)):
+                rs, gs, dx, drift = _check_cluster(orc, pos, vel, m, off, eps2, out, c, 1 / 16,
+                                                   1 / 16)
+                say("shape %r %s cluster %d N=%d: steps GPU %d oracle %d, max|dx| %.2e"
+                    % (shape, mode, c, sizes[c], gs, rs, dx))
+                assert abs(gs - rs) <= max(2, 0.03 * rs)
+                assert dx < 1e-6
+    finally:
+        nb.ensemble_set(**saved)
+
+
+def _rel(got, ref):
+    return np.linalg.norm(got - ref, axis=0) / np.linalg.norm(ref, axis=0)
+
+
+@pytest.mark.parametrize("mode", ["fp32", "ds"])
+def test_ensemble_force_accuracy_per_cluster(orc, mode):
+    # Per-cluster acceleration and jerk errors of the ensemble's pair sums
+    # against the oracle, for the smallest and largest clusters of the
+    # 256-cluster workload: at the initial state (a launch to t_end = 0 only
+    # initialises), and at an evolved state (the clusters integrated to
+    # t = 1/32 with dt_max = 1/32, so that every particle ends at 1/32, then
+    # initialised again there).  Gates per cluster: acceleration p99 <= 1e-6
+    # and max <= 1e-5, jerk p99 <= 1e-5 and max <= 1e-4 (float32 pair
+    # terms in both modes; the compensated mode adds TwoSum-folded sums).
+    need_gpu()
+    import paper_cs_0702135_amd as nb
+    cfg = CONFIGS["ensemble256"]
+    sizes, eps, seeds = ensemble_members(cfg)
+    pos, vel, m, off = _build(sizes, seeds)
+    eps2 = eps * eps
+    order = np.argsort(sizes)
+    pick = list(order[:3]) + list(order[-3:])
+    for label, t_mid in (("initial", None), ("t=1/32", 1.0 / 32)):
+        P, V = dev(pos), dev(vel)
+        if t_mid is not None:
+            st = nb.ensemble_run(P, V, dev(m), off, eps2, t_mid, dt_max=t_mid, mode=mode)
+            assert np.all(host(st["t"]) == t_mid)
+            P, V = st["x"], st["v"]
+        out = nb.ensemble_run(P, V, dev(m), off, eps2, 0.0, dt_max=cfg.dt_max, mode=mode)
+        x, v = host(P), host(V)
+        for c in pick:
+            a, b = off[c], off[c + 1]
+            ra, rk, _ = orc.force(x[:, a:b], v[:, a:b], m[a:b], eps2[c])
+            ea = _rel(host(out["a"])[:, a:b], ra)
+            ek = _rel(host(out["k"])[:, a:b], rk)
+            say("ensemble %s %s cluster %d N=%d: acc p99 %.2e max %.2e | jerk p99 %.2e max %.2e"
+                % (label, mode, c, sizes[c], np.percentile(ea, 99), ea.max(),
+                   np.percentile(ek, 99), ek.max()))
+            assert np.percentile(ea, 99) <= 1e-6 and ea.max() <= 1e-5
+            assert np.percentile(ek, 99) <= 1e-5 and ek.max() <= 1e-4

@@ -157,3 +157,33 @@ def test_native_chain_matches_per_step_autograd(mode):
     np.testing.assert_array_equal(res[0][0], res[1][0])
     for got, ref in zip(res[0][1:], res[1][1:]):
         np.testing.assert_allclose(got, ref, rtol=1e-12, atol=1e-12 * np.abs(ref).max())
+
+
+@pytest.mark.parametrize("mode", ["fp32", "ds"])
+def test_differentiable_run_forward_force_accuracy(orc, mode):
+    # Forward pair sums of the differentiable run (Plummer N = 16384,
+    # eps = 1/512, shared steps of 1/512): the acceleration and jerk left by
+    # step 8 are the pair sums at the state predicted from the state after
+    # step 7 (the corrector stores them), checked against the oracle's pair
+    # sums at that predicted state.  Gates: float32 mode acceleration p99
+    # <= 1e-6 and max <= 1e-5, jerk p99 <= 1e-5 and max <= 1e-4;
+    # compensated mode (float64 pair terms) p99 <= 1e-12 and max <= 1e-10.
+    need_gpu()
+    from paper_cs_0702135_amd.autograd import shared_run
+    cfg = CONFIGS["grad16k"]
+    pos, vel, m = plummer(cfg.n, cfg.seed)
+    h = cfg.extra["dt"]
+    P, V, M = dev(pos), dev(vel), dev(m)
+    x7, v7, a7, k7 = (host(q) for q in shared_run(P, V, M, cfg.eps2, h, 7, 0, mode))
+    x8, v8, a8, k8 = (host(q) for q in shared_run(P, V, M, cfg.eps2, h, 8, 0, mode))
+    t = np.zeros(cfg.n)
+    xp, vp = orc.predict(h, t, x7, v7, a7, k7)
+    ra, rk, _ = orc.force(xp, vp, m, cfg.eps2)
+    ea = np.linalg.norm(a8 - ra, axis=0) / np.linalg.norm(ra, axis=0)
+    ek = np.linalg.norm(k8 - rk, axis=0) / np.linalg.norm(rk, axis=0)
+    say("differentiable run %s, step 8: acc p50 %.2e p99 %.2e max %.2e | jerk p50 %.2e p99 %.2e "
+        "max %.2e" % (mode, np.median(ea), np.percentile(ea, 99), ea.max(), np.median(ek),
+                      np.percentile(ek, 99), ek.max()))
+    gates = {"fp32": (1e-6, 1e-5, 1e-5, 1e-4), "ds": (1e-12, 1e-10, 1e-12, 1e-10)}[mode]
+    assert np.percentile(ea, 99) <= gates[0] and ea.max() <= gates[1]
+    assert np.percentile(ek, 99) <= gates[2] and ek.max() <= gates[3]

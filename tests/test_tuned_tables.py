@@ -42,3 +42,6 @@ def test_ensemble_models_are_usable():
         assert c["groups_per_cu"] >= 1 and 1 <= c["max_team"] <= 64
         assert c["group_rate"] > 0 and c["steps_coef"] > 0
         assert c["step_us"] >= 0 and c["barrier_us"] >= 0 and c["barrier_group_us"] >= 0
+        # a workgroup shape the library compiles (autotune.ENS_SHAPES)
+        from paper_cs_0702135_amd.autotune import ENS_SHAPES
+        assert (c["waves"], c["j_tile"], c["i_per_lane"]) in ENS_SHAPES

@@ -131,6 +131,7 @@ CONFIGS = {
     # Plummer N=2^20, eps=1/4096; force-only sweep over n_i.
     "plummer1m": Config("plummer1m", 1 << 20, 1.0 / 4096, 1003,
                         extra={"n_i": (1024, 16384, 262144, 1 << 20),
+                               "n_i_small": (1, 16, 64),
                                "n_sample": 4096}),
     # Beyond 2^20: N = 9,000,000 (the paper's capacity claim for its GPU),
     # force-only on seeded active subsets; N = 2^22, a few block steps.
