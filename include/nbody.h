@@ -115,6 +115,22 @@ int nbody_force(nbody_ctx *ctx, const int32_t *active_idx, int64_t n_i,
                 int64_t n_j, double eps2, double *acc, double *jerk,
                 double *pot, uint32_t flags);
 
+/* ---- smallest-first float32 pair sums (Section 6) -----------------------
+ * The accuracy improvement Section 6 proposes for float32 sums: the same
+ * acceleration, jerk and potential as nbody_force, with every pair term
+ * evaluated in float64 and rounded once to float32, and each particle's
+ * terms added in float32 in ascending order of the pair-acceleration
+ * magnitude m_j |x_j - x_i| S^(-3/2) (ties by j), all seven sums in that
+ * order.  An accuracy mode, not a fast path: one workgroup per particle sorts
+ * its n_j - 1 keys in LDS.
+ *   n_j : 1 <= n_j <= 8192, else NBODY_E_INVAL.  Other arguments, layouts
+ *   and errors as nbody_force (no flags).  eps2 = 0 with coincident
+ *   particles gives non-finite keys and an unspecified order. */
+int nbody_force_sorted(nbody_ctx *ctx, const int32_t *active_idx, int64_t n_i,
+                       const double *pos, const double *vel, const double *mass,
+                       int64_t n_j, double eps2, double *acc, double *jerk,
+                       double *pot);
+
 /* ---- pair sums without allocation ----------------------------------------
  * For callers that cannot allocate device memory: code under HIP graph
  * capture, tight serving loops, harnesses that forbid hipMalloc.  Same

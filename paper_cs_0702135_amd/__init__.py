@@ -23,7 +23,8 @@ import torch
 from . import _lib as L
 
 __all__ = [
-    "NBodyError", "Context", "context", "force", "force_noalloc", "predict", "schedule",
+    "NBodyError", "Context", "context", "force", "force_sorted", "force_noalloc", "predict",
+    "schedule",
     "schedule_async", "predict_dev", "force_dev", "correct_dev",
     "correct", "initial_dt", "energy", "System", "ACC_FP32", "ACC_DS",
     "ForceShape", "tune_set", "tune_clear", "tune_get", "profile",
@@ -167,6 +168,28 @@ def force(pos, vel, mass, eps2, active_idx=None, mode="fp32", out=None):
     ctx.check(ctx.lib.nbody_force(ctx.bind(), _ptr(active_idx), n_i, _ptr(pos), _ptr(vel),
                                   _ptr(mass), n, float(eps2), _ptr(acc), _ptr(jerk),
                                   _ptr(pot), _mode(mode)))
+    return acc, jerk, pot
+
+
+def force_sorted(pos, vel, mass, eps2, active_idx=None):
+    """Smallest-first float32 pair sums (nbody_force_sorted, Section 6):
+    (acc (3, n_i), jerk (3, n_i), pot (n_i,)); n must not exceed 8192."""
+    n = mass.shape[0]
+    _vec(pos, n, "pos"), _vec(vel, n, "vel"), _sca(mass, n, "mass")
+    if active_idx is not None:
+        if active_idx.dtype != torch.int32 or not active_idx.is_cuda or active_idx.dim() != 1:
+            raise ValueError("active_idx must be a 1-d int32 CUDA tensor")
+        active_idx = active_idx.contiguous()
+        n_i = active_idx.shape[0]
+    else:
+        n_i = n
+    acc = torch.empty((3, n_i), dtype=torch.float64, device=pos.device)
+    jerk = torch.empty_like(acc)
+    pot = torch.empty((n_i,), dtype=torch.float64, device=pos.device)
+    ctx = context(pos.device)
+    ctx.check(ctx.lib.nbody_force_sorted(ctx.bind(), _ptr(active_idx), n_i, _ptr(pos), _ptr(vel),
+                                         _ptr(mass), n, float(eps2), _ptr(acc), _ptr(jerk),
+                                         _ptr(pot)))
     return acc, jerk, pot
 
 

@@ -72,6 +72,7 @@ SIGNATURES = {
     "nbody_sync_status": (INT, [P]),
     "nbody_force": (INT, [P, P, I64, P, P, P, I64, D, P, P, P, U32]),
     "nbody_force_noalloc": (INT, [P, P, I64, P, P, P, I64, D, P, P, P, U32]),
+    "nbody_force_sorted": (INT, [P, P, I64, P, P, P, I64, D, P, P, P]),
     "nbody_predict": (INT, [P, I64, D, P, P, P, P, P, P, P]),
     "nbody_schedule": (INT, [P, I64, P, P, P, P, P]),
     "nbody_correct": (INT, [P, I64, I64, P, P, P, P, P, D, D, D, INT, P, P, P, P,
