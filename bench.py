@@ -544,6 +544,26 @@ def main():
         aux["plummer1k_block_steps"] = steps1
         aux["plummer1k_ms_per_block_step"] = (tb - ta) / max(1, steps1) * 1e3
 
+        # cost of the smallest-first float32 sums (Section 6) against the
+        # float32 mode on the same full-N call, N = 1024 and N = 8192
+        sorted_cost = {}
+        for n_s in (1024, 8192):
+            ps, vs, ms = (torch.from_numpy(a).cuda() for a in plummer(n_s, c1.seed))
+            row = {}
+            for key, fn in (("sorted_ms", lambda: nb.force_sorted(ps, vs, ms, c1.eps2)),
+                            ("fp32_ms", lambda: nb.force(ps, vs, ms, c1.eps2, None, "fp32"))):
+                fn()
+                torch.cuda.synchronize()
+                e0.record()
+                for _ in range(3):
+                    fn()
+                e1.record()
+                torch.cuda.synchronize()
+                row[key] = e0.elapsed_time(e1) / 3
+            row["ratio"] = row["sorted_ms"] / row["fp32_ms"]
+            sorted_cost["n%d" % n_s] = row
+        aux["smallest_first_sorted_cost"] = sorted_cost
+
         # Plummer N=65536, eps=1/1024: full-N force-only throughput, then the
         # block-step run to t=1/8 (wall time, steps, energy drift)
         c2 = CONFIGS["plummer64k"]

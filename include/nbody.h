@@ -298,13 +298,20 @@ int nbody_ensemble_run(nbody_ctx *ctx, const nbody_ensemble *e, double t_end,
                        int64_t *steps, int64_t *interactions);
 
 /* Launch shape and team-planning model of the ensemble.  The persistent grid
- * has groups_per_cu workgroups per CU (capped by occupancy); a cluster of N
+ * has groups_per_cu workgroups per CU (capped by occupancy).  A cluster of N
  * particles is modelled to take S = steps_coef N^steps_exp t_end block steps
- * of 0.20 N^0.81 active particles (the paper fits 247 N^0.35 steps per time
- * unit and that block size), i.e. on a team of g groups
- *   T = S (step_us + [g > 1] (barrier_us + barrier_group_us g)) 1e-6
- *       + S 0.20 N^1.81 / (g group_rate),
- * and teams (at most min(max_team, 64) groups) are sized to even out T.
+ * with blocks of B = block_coef N^block_exp particles (the paper's fits,
+ * 247 N^0.35 steps per time unit and 0.20 N^0.81, are the defaults).  A pair
+ * pass over n_i particles costs the busiest group of a team of g groups
+ *   P(n_i) = tiles(n_i, g) tile_us 1e-6 + n_i N / (g group_rate),
+ * where tiles(n_i, g) counts the j tiles of its items under the kernel's
+ * split rule (items of 64 i_per_lane slots by S j ranges), and the cluster
+ *   T = P(N) + S (1e-6 (step_us + [g > 1] (barrier_us + barrier_group_us g))
+ *                + P(B)).
+ * The plan minimises the largest modelled team time: clusters that one group
+ * finishes in time share single-group teams (run one after the other), the
+ * others get teams of the fewest groups (at most min(max_team, 64)) that
+ * finish them in time, and spare groups go to the slowest teams.
  * The workgroup shape (waves, j_tile, i_per_lane) must be one of the
  * compiled ones: (4, 256, 2), (4, 256, 1), (2, 128, 2), (2, 256, 2),
  * (4, 512, 2), (8, 512, 2). */
@@ -320,6 +327,9 @@ typedef struct nbody_ensemble_config {
     int32_t waves;         /* waves per workgroup, sharing each j tile */
     int32_t j_tile;        /* j particles staged in LDS per tile */
     int32_t i_per_lane;    /* block slots per lane (1 or 2) */
+    double tile_us;        /* latency of one j tile of a pair item (load, predict, LDS) */
+    double block_coef;     /* mean block size = block_coef N^block_exp */
+    double block_exp;
 } nbody_ensemble_config;
 
 int nbody_ensemble_set(nbody_ctx *ctx, const nbody_ensemble_config *cfg);

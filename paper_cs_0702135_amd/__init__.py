@@ -429,7 +429,8 @@ def ensemble_run(pos, vel, mass, offsets, eps2, t_end, eta=0.02, eta_s=0.01, dt_
 
 def ensemble_set(groups_per_cu=None, max_team=None, step_us=None, barrier_us=None,
                  barrier_group_us=None, group_rate=None, steps_coef=None, steps_exp=None,
-                 waves=None, j_tile=None, i_per_lane=None, device=None):
+                 waves=None, j_tile=None, i_per_lane=None, tile_us=None, block_coef=None,
+                 block_exp=None, device=None):
     """Change the ensemble launch shape / team-planning model (None keeps)."""
     ctx = context(device)
     c = L.NBodyEnsembleConfig()
@@ -438,7 +439,8 @@ def ensemble_set(groups_per_cu=None, max_team=None, step_us=None, barrier_us=Non
                  ("barrier_us", barrier_us), ("barrier_group_us", barrier_group_us),
                  ("group_rate", group_rate),
                  ("steps_coef", steps_coef), ("steps_exp", steps_exp), ("waves", waves),
-                 ("j_tile", j_tile), ("i_per_lane", i_per_lane)):
+                 ("j_tile", j_tile), ("i_per_lane", i_per_lane), ("tile_us", tile_us),
+                 ("block_coef", block_coef), ("block_exp", block_exp)):
         if v is not None:
             setattr(c, k, v)
     ctx.check(ctx.lib.nbody_ensemble_set(ctx.h, ctypes.byref(c)))
@@ -484,7 +486,10 @@ def ensemble_plan(sizes, groups, t_end, config):
                                 float(config["barrier_group_us"]), float(config["group_rate"]),
                                 float(config["steps_coef"]), float(config["steps_exp"]),
                                 int(config.get("waves", 4)), int(config.get("j_tile", 256)),
-                                int(config.get("i_per_lane", 2)))
+                                int(config.get("i_per_lane", 2)),
+                                float(config.get("tile_us", 0.0)),
+                                float(config.get("block_coef", 0.20)),
+                                float(config.get("block_exp", 0.81)))
     team_of = _np.empty(nc, dtype=_np.int32)
     team_size = _np.empty(nc, dtype=_np.int32)
     secs = _np.empty(nc, dtype=_np.float64)

@@ -59,7 +59,7 @@ class NBodyEnsembleConfig(ctypes.Structure):
     _fields_ = [("groups_per_cu", I32), ("max_team", I32), ("step_us", D),
                 ("barrier_us", D), ("barrier_group_us", D), ("group_rate", D),
                 ("steps_coef", D), ("steps_exp", D), ("waves", I32), ("j_tile", I32),
-                ("i_per_lane", I32)]
+                ("i_per_lane", I32), ("tile_us", D), ("block_coef", D), ("block_exp", D)]
 
 
 # name -> (restype, argtypes); every symbol include/nbody.h declares

@@ -170,9 +170,10 @@ def load_or_tune(pos, vel, mass, eps2, mode="fp32", log=None, dynamic_n_i=None, 
 # representative launch: a synthetic ensemble drawn like the workload is run,
 # the per-cluster wall times the kernel records are fitted by least squares
 # (per-step latency and effective pair rate of a group on single-group
-# clusters, the team cost b0 + b1 g on multi-group ones, the block-step count
-# law c N^p on all), the teams are re-planned with the fitted model, and the
-# fastest of the measured launches is kept, for 2 and 3 groups per CU.
+# clusters, the team cost b0 + b1 g on multi-group ones, the block-step and
+# interaction laws c N^p on all), the teams are re-planned with the fitted
+# model, and the fastest of the measured launches is kept, for every compiled
+# shape at 2 and 3 waves per SIMD.
 
 def _ens_mixed_inputs():
     # 256 clusters drawn like the ensemble workload (log-uniform N in
@@ -206,35 +207,73 @@ def _ens_mixed_run(inp, mode, t_end, dt_max):
     return e0.elapsed_time(e1) * 1e-3, rows
 
 
+def ens_tiles(n_i, n, g, slots, tile, max_split=64):
+    """j tiles of the busiest group of a g-group team in a pair pass of n_i
+    slots over n particles, under the kernel's split rule: items of `slots`
+    block slots by S j ranges, S minimising ceil(nb S / g) / S (the
+    smallest on ties), S <= min(64, g) and S <= n / tile."""
+    nb = -(-int(n_i) // slots)
+    smax = max(1, min(max_split, g, n // tile))
+    best, bq = 1, -(-nb // g)
+    for S in range(2, smax + 1):
+        q = -(-(nb * S) // g)
+        if q * best < bq * S:
+            best, bq = S, q
+    jchunk = -(-n // best)
+    return bq * (-(-jchunk // tile))
+
+
 def _fit_model(rows, cfg, t_end):
-    """Least-squares fit of the time model to measured clusters of one launch."""
+    """Least-squares fit of the time model to measured clusters of one launch:
+    the block-step and block-size laws on all clusters; per-step latency,
+    tile latency and pair rate of one group on single-group clusters; the
+    extra per-step cost b0 + b1 g of a team on the others."""
     import numpy as np
     r = np.array(rows, dtype=np.float64)
     sec, g, n, st, it = r.T
     new = dict(cfg)
-    one = g == 1
-    if one.sum() >= 4:
-        A = np.stack([st[one], it[one]], axis=1)
-        sol, *_ = np.linalg.lstsq(A, sec[one], rcond=None)
-        if sol[0] > 0 and sol[1] > 0:
-            new["step_us"] = sol[0] * 1e6
-            new["group_rate"] = 1.0 / sol[1]
-    many = g > 1
-    if many.sum() >= 3:
-        rest = (sec[many] - st[many] * new["step_us"] * 1e-6
-                - it[many] / (g[many] * new["group_rate"])) / st[many]
-        A = np.stack([np.ones(many.sum()), g[many]], axis=1)
-        sol, *_ = np.linalg.lstsq(A, rest, rcond=None)
-        new["barrier_us"] = max(0.0, sol[0] * 1e6)
-        new["barrier_group_us"] = max(0.0, sol[1] * 1e6)
     ok = st > 0
     p, logc = np.polyfit(np.log(n[ok]), np.log(st[ok] / t_end), 1)
     new["steps_exp"], new["steps_coef"] = float(p), float(np.exp(logc))
-    return new
+    blk = it[ok] / st[ok] / n[ok]
+    p, logc = np.polyfit(np.log(n[ok]), np.log(blk), 1)
+    new["block_exp"], new["block_coef"] = float(min(max(p, 0.0), 1.0)), float(np.exp(logc))
+    slots, tile = 64 * int(cfg["i_per_lane"]), int(cfg["j_tile"])
+    # tiles of the busiest group over the run: the initial full pass plus
+    # every step at the cluster's mean block
+    tiles = np.array([ens_tiles(nn, int(nn), int(gg), slots, tile)
+                      + ss * ens_tiles(max(1, round(ii / max(ss, 1) / nn)), int(nn), int(gg),
+                                       slots, tile)
+                      for nn, gg, ss, ii in zip(n, g, st, it)], dtype=np.float64)
+    inter = it + n * n  # the steps' pairs plus the initial full pass
+    from scipy.optimize import nnls
+    one = g == 1
+    if one.sum() >= 4:
+        # non-negative least squares, columns scaled to unit norm
+        A = np.stack([st[one], tiles[one], inter[one]], axis=1)
+        sc = np.linalg.norm(A, axis=0)
+        sol, _ = nnls(A / sc, sec[one])
+        sol = sol / sc
+        if sol[2] > 0:
+            new["step_us"] = sol[0] * 1e6
+            new["tile_us"] = sol[1] * 1e6
+            new["group_rate"] = 1.0 / sol[2]
+    many = g > 1
+    if many.sum() >= 3:
+        rest = (sec[many] - st[many] * new["step_us"] * 1e-6 - tiles[many] * new["tile_us"] * 1e-6
+                - inter[many] / (g[many] * new["group_rate"])) / st[many]
+        A = np.stack([np.ones(many.sum()), g[many]], axis=1)
+        sc = np.linalg.norm(A, axis=0)
+        sol, _ = nnls(A / sc, rest)
+        sol = sol / sc
+        new["barrier_us"] = sol[0] * 1e6
+        new["barrier_group_us"] = sol[1] * 1e6
+    return {k: (float(v) if isinstance(v, (float, np.floating)) else v) for k, v in new.items()}
 
 
 ENS_FIELDS = ("groups_per_cu", "max_team", "step_us", "barrier_us", "barrier_group_us",
-              "group_rate", "steps_coef", "steps_exp", "waves", "j_tile", "i_per_lane")
+              "group_rate", "steps_coef", "steps_exp", "waves", "j_tile", "i_per_lane",
+              "tile_us", "block_coef", "block_exp")
 
 # Workgroup shapes of the ensemble kernel the library compiles:
 # (waves per group, j records per LDS tile, block slots per lane).
@@ -267,12 +306,13 @@ def calibrate_ensemble(mode="fp32", t_end=1.0 / 16, dt_max=1.0 / 16, log=None, r
                     cfg = _fit_model(rows, cfg, t_end)
         cfg = best[0]
         if log:
-            log("ensemble model: shape (%d waves, tile %d, %d per lane), step %.1f us, barrier "
-                "%.1f + %.2f g us, group rate %.3e /s, steps %.1f N^%.3f per time unit, "
-                "%d groups per CU (%.4f s)"
+            log("ensemble model: shape (%d waves, tile %d, %d per lane), step %.1f us, tile "
+                "%.2f us, barrier %.1f + %.2f g us, group rate %.3e /s, steps %.1f N^%.3f per "
+                "time unit, blocks %.3f N^%.3f, %d groups per CU (%.4f s)"
                 % (cfg["waves"], cfg["j_tile"], cfg["i_per_lane"], cfg["step_us"],
-                   cfg["barrier_us"], cfg["barrier_group_us"], cfg["group_rate"],
-                   cfg["steps_coef"], cfg["steps_exp"], cfg["groups_per_cu"], best[1]))
+                   cfg["tile_us"], cfg["barrier_us"], cfg["barrier_group_us"],
+                   cfg["group_rate"], cfg["steps_coef"], cfg["steps_exp"], cfg["block_coef"],
+                   cfg["block_exp"], cfg["groups_per_cu"], best[1]))
         cfg["calibration_seconds"] = best[1]
         return cfg
     finally:

@@ -84,7 +84,8 @@ struct nbody_ctx {
     size_t ens_bytes = 0;
     void *static_scratch = nullptr;  // this device's copy of the static scratch
     int static_scratch_rc = 0;       // hipGetSymbolAddress status (hipError_t)
-    nbody_ensemble_config ens_cfg = {2, 64, 30.0, 15.0, 0.5, 2.0e9, 247.0, 0.35, 4, 256, 2};
+    nbody_ensemble_config ens_cfg = {2, 64, 30.0, 15.0, 0.5, 2.0e9, 247.0, 0.35, 4, 256, 2,
+                                      0.0, 0.20, 0.81};
     int ens_last_grid = 0;
     int ens_last_teams = 0;
     std::vector<double> ens_last_seconds;  // per cluster, last ensemble launch

@@ -263,7 +263,9 @@ int nbody_ensemble_set(nbody_ctx *ctx, const nbody_ensemble_config *cfg) {
         !(cfg->barrier_group_us >= 0) || std::isinf(cfg->barrier_group_us) ||
         !(cfg->group_rate > 0) || std::isinf(cfg->step_us) || std::isinf(cfg->barrier_us) ||
         std::isinf(cfg->group_rate) || !(cfg->steps_coef > 0) || !(cfg->steps_exp >= 0) ||
-        !(cfg->steps_exp < 3) || std::isinf(cfg->steps_coef))
+        !(cfg->steps_exp < 3) || std::isinf(cfg->steps_coef) || !(cfg->tile_us >= 0) ||
+        std::isinf(cfg->tile_us) || !(cfg->block_coef > 0) || std::isinf(cfg->block_coef) ||
+        !(cfg->block_exp >= 0) || !(cfg->block_exp <= 1))
         return fail(ctx, NBODY_E_INVAL, "nbody_ensemble_set: bad values");
     if (!find_variant(cfg->waves, cfg->j_tile, cfg->i_per_lane))
         return fail(ctx, NBODY_E_INVAL,

@@ -4,10 +4,11 @@
 // Every workgroup of the grid is co-resident (cooperative launch).  The
 // groups are partitioned into teams; a team owns a list of clusters and
 // integrates them one after the other, each from initialisation (pair sums
-// of every particle, initial steps) to t_end.  Within a team, each phase of
-// a block step (block selection, pair sums, split reduction, correction) is
-// spread over the team's groups and closed by a team barrier (one arrival
-// word per group in global memory, agent-scope release/acquire).  Barrier
+// of every particle, initial steps) to t_end.  Within a team, the two phases
+// of a block step (block selection and pair sums; split reduction and
+// correction) are spread over the team's groups and each is closed by a team
+// barrier (one arrival word per group in global memory, agent-scope
+// release/acquire).  Barrier
 // waits are bounded by a wall-clock limit: if one expires the launch raises
 // an abort flag that every group checks, so the grid always drains.
 //
@@ -19,11 +20,10 @@
 //     T(N, g) = S (step + [g > 1] (b0 + b1 g) + 0.20 N^1.81 / (g rate))
 // where step is the fixed latency of one block step on one group, b0 + b1 g
 // the extra cost of a step of a team of g groups and rate the pair
-// interactions per second of one group (all calibrated by the autotuner).  With at
-// least as many groups as clusters every cluster gets its own team and the
-// spare groups go, one at a time, to the team with the largest T (while
-// that lowers it); otherwise clusters are packed onto single-group teams,
-// longest first onto the least-loaded team.
+// interactions per second of one group (all calibrated by the autotuner).
+// The plan minimises the modelled makespan: clusters that one group
+// finishes in time share single-group teams, the others get the fewest
+// groups that finish them in time, and spare groups go to the slowest teams.
 //
 // The j particles of a pair-sum pass are staged through LDS in tiles (the
 // state is rewritten during this launch, so it cannot be read through the
@@ -157,28 +157,15 @@ __device__ __forceinline__ void ds_fold(float &hi, float &lo, float x, bool ds) 
     }
 }
 
-// Members of an active block.  Each group of a team compacts the members in
-// its own slice [p0(r), p1(r)) of the cluster, ascending, to act[p0(r)...];
-// pre[r] (in LDS) counts the members of the slices of groups 0..r-1, so block
-// slot s belongs to the group r with pre[r] <= s < pre[r + 1].  A null act
-// stands for the whole cluster in index order.
+// Members of an active block, ascending: every group of a team compacts
+// the whole cluster into its own copy act[0..n_i) (block slot s is particle
+// act[s]).  A null act stands for the whole cluster in index order.
 struct Block {
     const int32_t *act;
-    const int *pre;  // g + 1 entries
-    int g, per, n;
 };
 
 __device__ __forceinline__ int block_member(const Block &B, int s) {
-    if (!B.act) return s;
-    int lo = 0, hi = B.g;
-    while (hi - lo > 1) {
-        const int mid = (lo + hi) >> 1;
-        if (B.pre[mid] <= s)
-            lo = mid;
-        else
-            hi = mid;
-    }
-    return B.act[min(B.n, lo * B.per) + (s - B.pre[lo])];
+    return B.act ? B.act[s] : s;
 }
 
 // State of one particle as loaded, before prediction.
@@ -389,22 +376,38 @@ __device__ __forceinline__ int item_width(int rem, bool narrow) {
     return narrow ? w : max(w, 64);
 }
 
+// The j split of a block of n_i slots on a team of g groups.  The block is
+// cut into nb i-items of 64 IT slots and each into S j ranges; the S that
+// minimises the items of the busiest group per split, ceil(nb S / g) / S
+// (the busiest group's share of the work), is taken, the smallest on ties,
+// with at most s_max splits and no split below one tile.
+template <class Sh>
+__device__ __forceinline__ int ens_splits(int n_i, int n, int g, int s_max) {
+    const int nb = (n_i + 64 * Sh::IT - 1) / (64 * Sh::IT);
+    const int smax = max(1, min(s_max, n / Sh::TILE));
+    int best = 1, bq = (nb + g - 1) / g;  // cost ceil(nb S / g) / S as bq / best
+    for (int S = 2; S <= smax; ++S) {
+        const int q = (nb * S + g - 1) / g;
+        if ((int64_t)q * best < (int64_t)bq * S) {
+            best = S;
+            bq = q;
+        }
+    }
+    return best;
+}
+
 // Pair sums of a whole block (n_i slots) of a cluster of n particles,
-// spread over the team: results in anew/knew (slot-major, component stride
-// n_max); returns false on abort.  Items are 128 slots apart; the last one
-// is as narrow as its remainder allows.
+// spread over the team as items (128 slots by one of S j ranges).  With
+// S = 1 an item writes the slot's sums to anew/knew (component stride
+// n_max), otherwise its split's partial sums to part; share_sums adds the S
+// partials of a slot in split order once the team has passed a barrier.
 template <class Sh, bool DS, bool PRED>
-__device__ bool ens_pairs(const EnsArgs &A, int64_t base, int n, float eps2, double tn,
-                          const Block &B, int n_i, int g, int rank, int s_max, int n_max,
-                          double *anew, double *knew, double *part, uint32_t *bar,
-                          uint32_t &epoch, TileRec *tile, double (*red)[6 * Sh::IT][64]) {
-    if (n_i < 1) return team_barrier(bar, g, rank, epoch, A.abort, A.spin_limit);
+__device__ void ens_pairs(const EnsArgs &A, int64_t base, int n, float eps2, double tn,
+                          const Block &B, int n_i, int g, int rank, int S, int n_max,
+                          double *anew, double *knew, double *part, TileRec *tile,
+                          double (*red)[6 * Sh::IT][64]) {
+    if (n_i < 1) return;
     const int64_t nb = (n_i + 64 * Sh::IT - 1) / (64 * Sh::IT);
-    int64_t S = (g + nb - 1) / nb;  // about one item per group
-    int64_t smax = max(1, n / Sh::TILE);
-    if (smax > s_max) smax = s_max;
-    if (S > smax) S = smax;
-    if (S < 1) S = 1;
     const int64_t items = nb * S;
     const int jchunk = (int)((n + S - 1) / S);
     const int lane = threadIdx.x & 63;
@@ -453,52 +456,68 @@ __device__ bool ens_pairs(const EnsArgs &A, int64_t base, int n, float eps2, dou
             }
         }
     }
-    if (S > 1) {
-        if (!team_barrier(bar, g, rank, epoch, A.abort, A.spin_limit)) return false;
-        const int64_t total = 6 * (int64_t)n_i;
-        for (int64_t e = (int64_t)rank * Sh::TH + threadIdx.x; e < total;
-             e += (int64_t)g * Sh::TH) {
-            const int c = (int)(e / n_i), s = (int)(e - (int64_t)c * n_i);
-            double acc = 0.0;
-            for (int64_t p = 0; p < S; ++p) acc += part[(p * 6 + c) * n_max + s];
-            if (c < 3)
-                anew[c * n_max + s] = acc;
-            else
-                knew[(c - 3) * n_max + s] = acc;
+}
+
+// Acceleration and jerk of block slots [b0, b0 + cnt), cnt <= TH: with
+// S = 1 the item sums, otherwise the S partial sums of each slot added in
+// float64 in split order, one (slot, component) per thread with the partial
+// loads batched; the six components of slot b0 + l land in buf[c * TH + l].
+template <class Sh>
+__device__ __forceinline__ void share_sums(int b0, int cnt, int S, int n_max, const double *anew,
+                                           const double *knew, const double *part, double *buf) {
+    for (int e = threadIdx.x; e < 6 * cnt; e += Sh::TH) {
+        const int c = e / cnt, l = e - c * cnt, s = b0 + l;
+        double acc;
+        if (S == 1) {
+            acc = c < 3 ? anew[c * n_max + s] : knew[(c - 3) * n_max + s];
+        } else {
+            const double *pp = part + (int64_t)c * n_max + s;
+            const int64_t stride = 6 * (int64_t)n_max;
+            acc = 0.0;
+            int p = 0;
+            for (; p + 4 <= S; p += 4) {
+                const double v0 = pp[p * stride], v1 = pp[(p + 1) * stride];
+                const double v2 = pp[(p + 2) * stride], v3 = pp[(p + 3) * stride];
+                acc += v0;
+                acc += v1;
+                acc += v2;
+                acc += v3;
+            }
+            for (; p < S; ++p) acc += pp[p * stride];
         }
+        buf[c * Sh::TH + l] = acc;
     }
-    return team_barrier(bar, g, rank, epoch, A.abort, A.spin_limit);
+    __syncthreads();
 }
 
-__device__ __forceinline__ void store_relaxed(double *p, double v) {
-    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-__device__ __forceinline__ double load_relaxed(const double *p) {
-    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-
-// One block step of a cluster is three team phases, each closed by a team
+// One block step of a cluster is two team phases, each closed by a team
 // barrier:
-//   A  every group scans its slice once: it compacts the members of the
-//      block (t_i + dt_i == t_next) and takes the minimum of t_i + dt_i over
-//      the others, which do not move in this step;
-//   B  pair sums of the block, every particle predicted to t_next as it is
-//      loaded (no predicted copy of the state is stored);
-//   C  every group corrects the members of its own slice (predicting them
-//      again, bitwise the same) and takes the minimum of their new t + dt.
-// The next t_next is the minimum over the groups of both minima, so the
-// block time needs no pass of its own.  The per-group minima are
-// double-buffered by step parity: a group may publish the next step's
-// values while a slower one still reads this step's.
+//   B  every group finds the block on its own: t_next is the smaller of the
+//      least t + dt among the particles the last step did not move (known
+//      from the last scan) and the least new t + dt that the groups
+//      published in the last correction; one pass over the cluster's t + dt
+//      then compacts the members (t + dt == t_next), ascending, into the
+//      group's own member list and takes the least t + dt of the others;
+//      then the pair sums of the block, every particle predicted to t_next
+//      as it is loaded (no predicted copy of the state is stored);
+//   C  every group takes a contiguous share of the block's slots, adds their
+//      split partial sums, corrects them (predicting them again, bitwise the
+//      same) and publishes the least new t + dt of its share.
+// t + dt changes in phase C alone, and every group reaches phase C of a step
+// only after every group has finished that step's scan, so the groups always
+// see the same block.
 template <class Sh, bool DS>
 __global__ __launch_bounds__(Sh::TH, 3) void ensemble_kernel(const EnsArgs A) {
     constexpr int ETH = Sh::TH;
     constexpr int EW = Sh::W;
+    constexpr int SCAN = 8;  // particles per thread and pass of the block scan
     __shared__ TileRec tile[Sh::TILE];
     __shared__ double red[EW - 1][6 * Sh::IT][64];
     __shared__ double smin[EW];
-    __shared__ int scount[4 * EW];
-    __shared__ int spre[65];
+    __shared__ int scount[SCAN * EW];
+    // the slot sums of phase C reuse the tile (6 TH doubles <= 8 TILE)
+    static_assert(6 * Sh::TH <= 8 * Sh::TILE, "slot sums fit the tile");
+    double *sbuf = reinterpret_cast<double *>(tile);
     const int team = A.wg_team[blockIdx.x];
     const int rank = A.wg_rank[blockIdx.x];
     const EnsTeam T = A.teams[team];
@@ -507,15 +526,15 @@ __global__ __launch_bounds__(Sh::TH, 3) void ensemble_kernel(const EnsArgs A) {
     uint32_t epoch = 0;
     double *scr = A.scratch + T.scratch_off;
     const int n_max = T.n_max;
-    // scratch layout (doubles): pm[2 parities][2 kinds][g] | pcnt[g] (int32)
-    // | act[n_max] (int32) | anew[3 n_max] | knew[3 n_max] |
-    // part[s_max * 6 * n_max]
-    double *pm = scr;
-    int32_t *pcnt = (int32_t *)(scr + 4 * g);
-    int32_t *act = (int32_t *)(scr + 5 * g);
-    double *anew = scr + 5 * g + (n_max + 1) / 2;
+    // scratch layout (doubles): pmin[64] | tnext[n_max] | anew[3 n_max] |
+    // knew[3 n_max] | part[s_max * 6 * n_max] | act[g][n_max] (int32, one
+    // member list per group)
+    double *pmin = scr;
+    double *tnext = scr + 64;
+    double *anew = tnext + n_max;
     double *knew = anew + 3 * (int64_t)n_max;
     double *part = knew + 3 * (int64_t)n_max;
+    int32_t *act = (int32_t *)(part + (int64_t)T.s_max * 6 * n_max) + (int64_t)rank * n_max;
     const int64_t nt = A.nt;
     const int tid = threadIdx.x;
     const int lane = tid & 63, wave = tid >> 6;
@@ -526,74 +545,80 @@ __global__ __launch_bounds__(Sh::TH, 3) void ensemble_kernel(const EnsArgs A) {
         const int64_t base = C.off;
         const int n = C.n;
         const float eps2 = C.eps2;
-        const int per = (n + g - 1) / g;
-        const int p0 = min(n, rank * per), p1 = min(n, p0 + per);
         if (rank == 0 && tid == 0) A.clock[2 * c] = wall_clock64();
 
         // ---- initialisation: pair sums of every particle, initial steps
-        const Block whole{nullptr, spre, g, per, n};
-        if (!ens_pairs<Sh, DS, false>(A, base, n, eps2, 0.0, whole, n, g, rank, T.s_max, n_max,
-                                      anew, knew, part, bar, epoch, tile, red))
-            return;
-        double mn = INFINITY;
-        for (int i = p0 + tid; i < p1; i += ETH) {
-            const int64_t q = base + i;
+        {
+            const int S = ens_splits<Sh>(n, n, g, T.s_max);
+            ens_pairs<Sh, DS, false>(A, base, n, eps2, 0.0, Block{nullptr}, n, g, rank, S,
+                                     n_max, anew, knew, part, tile, red);
+            if (!team_barrier(bar, g, rank, epoch, A.abort, A.spin_limit)) return;
+            const int per = (n + g - 1) / g;
+            const int s0 = min(n, rank * per), s1 = min(n, s0 + per);
+            double mn = INFINITY;
+            for (int b0 = s0; b0 < s1; b0 += ETH) {
+                const int cnt = min(ETH, s1 - b0);
+                share_sums<Sh>(b0, cnt, S, n_max, anew, knew, part, sbuf);
+                if (tid < cnt) {
+                    const int i = b0 + tid;
+                    const int64_t q = base + i;
 #pragma unroll
-            for (int cc = 0; cc < 3; ++cc) {
-                A.a[cc * nt + q] = anew[cc * n_max + i];
-                A.k[cc * nt + q] = knew[cc * n_max + i];
+                    for (int cc = 0; cc < 3; ++cc) {
+                        A.a[cc * nt + q] = sbuf[cc * ETH + tid];
+                        A.k[cc * nt + q] = sbuf[(3 + cc) * ETH + tid];
+                    }
+                    int32_t st = 0;
+                    A.t[q] = 0.0;
+                    const double d =
+                        initial_dt_one(q, nt, 0.0, A.a, A.k, A.eta_s, A.dt_max, A.dt_min, &st);
+                    A.dt[q] = d;
+                    tnext[i] = 0.0 + d;
+                    mn = fmin(mn, 0.0 + d);
+                    if (st) atomicOr(A.status, st);
+                }
+                __syncthreads();
             }
-            int32_t st = 0;
-            A.t[q] = 0.0;
-            const double d = initial_dt_one(q, nt, 0.0, A.a, A.k, A.eta_s, A.dt_max, A.dt_min,
-                                            &st);
-            A.dt[q] = d;
-            mn = fmin(mn, 0.0 + d);
-            if (st) atomicOr(A.status, st);
+            mn = group_min<Sh>(mn, smin);
+            if (tid == 0) pmin[rank] = mn;
+            if (!team_barrier(bar, g, rank, epoch, A.abort, A.spin_limit)) return;
         }
-        mn = group_min<Sh>(mn, smin);
-        if (tid == 0) {
-            store_relaxed(&pm[rank], INFINITY);
-            store_relaxed(&pm[g + rank], mn);
-        }
-        if (!team_barrier(bar, g, rank, epoch, A.abort, A.spin_limit)) return;
 
         int64_t my_steps = 0, my_inter = 0;
-        int par = 0;
+        double rest = INFINITY;  // least t + dt of the particles the last step left alone
         for (;;) {
-            double tn = INFINITY;
-            for (int r = 0; r < g; ++r)
-                tn = fmin(tn, fmin(load_relaxed(&pm[(2 * par) * g + r]),
-                                   load_relaxed(&pm[(2 * par + 1) * g + r])));
+            // ---- B: the block time, the block's members, their pair sums
+            double tn = rest;
+            if (tid < 64) {
+                double v = tid < g ? pmin[tid] : INFINITY;
+#pragma unroll
+                for (int o = 32; o >= 1; o >>= 1) v = fmin(v, __shfl_xor(v, o, 64));
+                if (tid == 0) smin[0] = v;
+            }
+            __syncthreads();
+            tn = fmin(tn, smin[0]);
             if (!(tn <= A.t_end)) break;
-            const int nx = par ^ 1;
-
-            // ---- A: the block's members in the slice, ascending, and the
-            // minimum of t + dt over the rest of the slice
-            int local = 0;
+            int n_i = 0;
             double rmin = INFINITY;
             const unsigned long long below = (1ull << lane) - 1ull;
-            for (int pb = p0; pb < p1; pb += 4 * ETH) {
-                bool f[4];
+            for (int pb = 0; pb < n; pb += SCAN * ETH) {
+                double s[SCAN];
 #pragma unroll
-                for (int u = 0; u < 4; ++u) {
+                for (int u = 0; u < SCAN; ++u) {
                     const int i = pb + u * ETH + tid;
-                    f[u] = false;
-                    if (i < p1) {
-                        const double s = A.t[base + i] + A.dt[base + i];
-                        f[u] = (s == tn);
-                        if (!f[u]) rmin = fmin(rmin, s);
-                    }
+                    s[u] = i < n ? tnext[i] : INFINITY;
                 }
-                unsigned long long bal[4];
+                bool f[SCAN];
+                unsigned long long bal[SCAN];
 #pragma unroll
-                for (int u = 0; u < 4; ++u) {
+                for (int u = 0; u < SCAN; ++u) {
+                    f[u] = (s[u] == tn);
+                    if (!f[u]) rmin = fmin(rmin, s[u]);
                     bal[u] = __ballot(f[u]);
                     if (lane == 0) scount[u * EW + wave] = __popcll(bal[u]);
                 }
                 __syncthreads();
 #pragma unroll
-                for (int u = 0; u < 4; ++u) {
+                for (int u = 0; u < SCAN; ++u) {
                     int woff = 0, tot = 0;
 #pragma unroll
                     for (int w = 0; w < EW; ++w) {
@@ -601,64 +626,51 @@ __global__ __launch_bounds__(Sh::TH, 3) void ensemble_kernel(const EnsArgs A) {
                         woff += (w < wave) ? cw : 0;
                         tot += cw;
                     }
-                    if (f[u]) act[p0 + local + woff + __popcll(bal[u] & below)] = pb + u * ETH + tid;
-                    local += tot;
+                    if (f[u]) act[n_i + woff + __popcll(bal[u] & below)] = pb + u * ETH + tid;
+                    n_i += tot;
                 }
                 __syncthreads();
             }
-            rmin = group_min<Sh>(rmin, smin);
-            if (tid == 0) {
-                store_relaxed(&pm[(2 * nx) * g + rank], rmin);
-                __hip_atomic_store(&pcnt[rank], local, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            }
+            rest = group_min<Sh>(rmin, smin);
+            const int S = ens_splits<Sh>(n_i, n, g, T.s_max);
+            ens_pairs<Sh, DS, true>(A, base, n, eps2, tn, Block{act}, n_i, g, rank, S, n_max,
+                                    anew, knew, part, tile, red);
             if (!team_barrier(bar, g, rank, epoch, A.abort, A.spin_limit)) return;
-            if (tid < 64) {
-                int cs = tid < g ? __hip_atomic_load(&pcnt[tid], __ATOMIC_RELAXED,
-                                                     __HIP_MEMORY_SCOPE_AGENT)
-                                 : 0;
-#pragma unroll
-                for (int o = 1; o < 64; o <<= 1) {
-                    const int y = __shfl_up(cs, o, 64);
-                    cs += (lane >= o) ? y : 0;
-                }
-                spre[tid + 1] = cs;
-                if (tid == 0) spre[0] = 0;
-            }
-            __syncthreads();
-            const int n_i = spre[g];
-            const Block blk{act, spre, g, per, n};
 
-            // ---- B: pair sums of the block at the predicted state
-            if (!ens_pairs<Sh, DS, true>(A, base, n, eps2, tn, blk, n_i, g, rank, T.s_max, n_max,
-                                         anew, knew, part, bar, epoch, tile, red))
-                return;
-
-            // ---- C: correct the slice's members; minimum of the new t + dt
-            const int s_own = spre[rank];
+            // ---- C: correct this group's share of the block's slots
+            const int per = (n_i + g - 1) / g;
+            const int s0 = min(n_i, rank * per), s1 = min(n_i, s0 + per);
             double nmin = INFINITY;
-            for (int kk = tid; kk < local; kk += ETH) {
-                const int s = s_own + kk;
-                const int64_t q = base + act[p0 + kk];
-                Raw r;
-                load_raw<true>(A, q, r);
-                double px[3], pv[3];
-                raw_state<true>(r, tn, px, pv);
-                double a1v[3], k1v[3];
+            for (int b0 = s0; b0 < s1; b0 += ETH) {
+                const int cnt = min(ETH, s1 - b0);
+                share_sums<Sh>(b0, cnt, S, n_max, anew, knew, part, sbuf);
+                if (tid < cnt) {
+                    const int i = act[b0 + tid];
+                    const int64_t q = base + i;
+                    Raw r;
+                    load_raw<true>(A, q, r);
+                    double px[3], pv[3];
+                    raw_state<true>(r, tn, px, pv);
+                    double a1v[3], k1v[3];
 #pragma unroll
-                for (int cc = 0; cc < 3; ++cc) {
-                    a1v[cc] = anew[cc * n_max + s];
-                    k1v[cc] = knew[cc * n_max + s];
+                    for (int cc = 0; cc < 3; ++cc) {
+                        a1v[cc] = sbuf[cc * ETH + tid];
+                        k1v[cc] = sbuf[(3 + cc) * ETH + tid];
+                    }
+                    double tq;
+                    const int32_t st =
+                        correct_vals(q, nt, px, pv, a1v, k1v, A.eta, A.dt_max, A.dt_min, 0, A.t,
+                                     A.dt, A.x, A.v, A.a, A.k, &tq);
+                    if (st) atomicOr(A.status, st);
+                    tnext[i] = tq;
+                    nmin = fmin(nmin, tq);
                 }
-                const int32_t st = correct_vals(q, nt, px, pv, a1v, k1v, A.eta, A.dt_max,
-                                                A.dt_min, 0, A.t, A.dt, A.x, A.v, A.a, A.k);
-                if (st) atomicOr(A.status, st);
-                nmin = fmin(nmin, A.t[q] + A.dt[q]);
+                __syncthreads();
             }
             nmin = group_min<Sh>(nmin, smin);
-            if (tid == 0) store_relaxed(&pm[(2 * nx + 1) * g + rank], nmin);
+            if (tid == 0) pmin[rank] = nmin;
             my_steps += 1;
             my_inter += (int64_t)n_i * n;
-            par = nx;
             if (!team_barrier(bar, g, rank, epoch, A.abort, A.spin_limit)) return;
         }
         if (rank == 0 && tid == 0) {
@@ -716,70 +728,154 @@ struct Plan {
 };
 
 struct TimeModel {
-    double step_s, barrier_s, barrier_g_s, rate, t_end, coef, expo;
+    double step_s, barrier_s, barrier_g_s, rate, t_end, coef, expo, tile_s, bcoef, bexpo;
+    int slots, tile;  // block slots per item (64 i_per_lane), j records per tile
     double steps(double n) const { return std::max(1.0, coef * std::pow(n, expo) * t_end); }
+    double block(double n) const { return std::min(n, std::max(1.0, bcoef * std::pow(n, bexpo))); }
+    // j tiles of the busiest group in a pair pass of n_i slots (the kernel's
+    // split rule, ens_splits)
+    double tiles(int64_t n_i, int64_t n, int g) const {
+        const int64_t nb = (n_i + slots - 1) / slots;
+        const int64_t smax = std::max<int64_t>(1, std::min<int64_t>(std::min(EMAXSPLIT, g), n / tile));
+        int64_t best = 1, bq = (nb + g - 1) / g;
+        for (int64_t S = 2; S <= smax; ++S) {
+            const int64_t q = (nb * S + g - 1) / g;
+            if (q * best < bq * S) {
+                best = S;
+                bq = q;
+            }
+        }
+        const int64_t jchunk = (n + best - 1) / best;
+        return (double)(bq * ((jchunk + tile - 1) / tile));
+    }
+    double pass(double n_i, double n, int g) const {
+        return tiles((int64_t)std::ceil(n_i), (int64_t)n, g) * tile_s + n_i * n / ((double)g * rate);
+    }
     double time(double n, int g) const {
-        const double per_step = step_s + (g > 1 ? barrier_s + barrier_g_s * g : 0.0) +
-                                0.20 * std::pow(n, 1.81) / ((double)g * rate);
-        return steps(n) * per_step;
+        return pass(n, n, g) + steps(n) * (step_s + (g > 1 ? barrier_s + barrier_g_s * g : 0.0) +
+                                           pass(block(n), n, g));
+    }
+    static TimeModel of(const nbody_ensemble_config &c, double t_end) {
+        return TimeModel{c.step_us * 1e-6,  c.barrier_us * 1e-6, c.barrier_group_us * 1e-6,
+                         c.group_rate,      t_end,              c.steps_coef,
+                         c.steps_exp,       c.tile_us * 1e-6,   c.block_coef,
+                         c.block_exp,       64 * c.i_per_lane,  c.j_tile};
     }
 };
 
+// Team plan of least modelled makespan.  For a target time T every cluster
+// needs the fewest groups g(T) whose modelled time is within T; the clusters
+// that one group finishes within T are packed onto shared single-group teams
+// (first fit, longest first: a team runs its clusters one after the other),
+// the others get teams of g(T) groups.  T is bisected down to the least
+// value whose plan fits the grid; the groups left over then go, one at a
+// time, to the team with the longest modelled time while that shortens it.
 static Plan plan_teams(const std::vector<int64_t> &sizes, int G, int max_team,
                        const TimeModel &M) {
     const int nc = (int)sizes.size();
+    // modelled time of every cluster on 1 .. max_team groups
+    std::vector<double> tab((size_t)nc * max_team);
+    for (int c = 0; c < nc; ++c)
+        for (int g = 1; g <= max_team; ++g)
+            tab[(size_t)c * max_team + g - 1] = M.time((double)sizes[c], g);
+    auto tm = [&](int c, int g) { return tab[(size_t)c * max_team + g - 1]; };
+    std::vector<double> t1(nc);
+    double lo = 0.0, hi = 0.0;
+    for (int c = 0; c < nc; ++c) {
+        t1[c] = tm(c, 1);
+        double best = t1[c];
+        for (int g = 2; g <= max_team; ++g) best = std::min(best, tm(c, g));
+        lo = std::max(lo, best);
+        hi += t1[c];
+    }
+    std::vector<int> by_t1(nc);
+    std::iota(by_t1.begin(), by_t1.end(), 0);
+    std::sort(by_t1.begin(), by_t1.end(), [&](int p, int q) {
+        return t1[p] > t1[q] || (t1[p] == t1[q] && p < q);
+    });
+    std::vector<int> gsz(nc);
+    std::vector<std::vector<int>> bins;
+    std::vector<double> bin_load;
+    // groups that the plan for target T needs (gsz, bins filled), or -1
+    auto build = [&](double T) -> int64_t {
+        int64_t used = 0;
+        bins.clear();
+        bin_load.clear();
+        for (int c = 0; c < nc; ++c) {
+            gsz[c] = 0;
+            if (t1[c] <= T) continue;  // packed below
+            int g = 2;
+            while (g <= max_team && tm(c, g) > T) ++g;
+            if (g > max_team) return -1;
+            gsz[c] = g;
+            used += g;
+        }
+        for (int c : by_t1) {
+            if (gsz[c] != 0) continue;
+            gsz[c] = 1;
+            size_t b = 0;
+            while (b < bins.size() && bin_load[b] + t1[c] > T) ++b;
+            if (b == bins.size()) {
+                bins.push_back({});
+                bin_load.push_back(0.0);
+            }
+            bins[b].push_back(c);
+            bin_load[b] += t1[c];
+        }
+        return used + (int64_t)bins.size();
+    };
+    for (int it = 0; it < 60 && hi - lo > 1e-7 * hi; ++it) {
+        const double mid = 0.5 * (lo + hi);
+        const int64_t u = build(mid);
+        if (u >= 0 && u <= G)
+            hi = mid;
+        else
+            lo = mid;
+    }
+    build(hi);
+
     std::vector<std::vector<int>> tcl;
     std::vector<int> tsize;
-    if (G >= nc) {
-        // one team per cluster, then spare groups to the slowest team
-        std::vector<int> gsz(nc, 1);
-        typedef std::pair<double, int> TT;
-        std::priority_queue<TT> heap;
-        for (int c = 0; c < nc; ++c) heap.push(TT(M.time((double)sizes[c], 1), c));
-        int spare = G - nc;
-        while (spare > 0 && !heap.empty()) {
-            TT top = heap.top();
-            heap.pop();
-            const int c = top.second;
-            if (gsz[c] >= max_team) continue;
-            const double t1 = M.time((double)sizes[c], gsz[c] + 1);
-            if (!(t1 < top.first)) continue;  // more groups no longer help
-            gsz[c] += 1;
-            --spare;
-            heap.push(TT(t1, c));
-        }
-        std::vector<int> idx(nc);
-        std::iota(idx.begin(), idx.end(), 0);
-        std::sort(idx.begin(), idx.end(), [&](int p, int q) {
-            const double a = M.time((double)sizes[p], gsz[p]), b = M.time((double)sizes[q], gsz[q]);
-            return a > b || (a == b && p < q);
-        });
-        for (int c : idx) {
+    for (int c = 0; c < nc; ++c)
+        if (gsz[c] > 1) {
             tcl.push_back({c});
             tsize.push_back(gsz[c]);
         }
-    } else {
-        // more clusters than groups: longest first onto the least-loaded group
-        std::vector<int> idx(nc);
-        std::iota(idx.begin(), idx.end(), 0);
-        std::sort(idx.begin(), idx.end(), [&](int p, int q) {
-            return sizes[p] > sizes[q] || (sizes[p] == sizes[q] && p < q);
-        });
-        tcl.assign(G, {});
-        tsize.assign(G, 1);
-        typedef std::pair<double, int> LT;
-        std::priority_queue<LT, std::vector<LT>, std::greater<LT>> heap;
-        for (int t = 0; t < G; ++t) heap.push(LT(0.0, t));
-        for (int c : idx) {
-            LT top = heap.top();
-            heap.pop();
-            tcl[top.second].push_back(c);
-            heap.push(LT(top.first + M.time((double)sizes[c], 1), top.second));
-        }
+    for (const std::vector<int> &b : bins) {
+        tcl.push_back(b);
+        tsize.push_back(1);
     }
+    const int nteam = (int)tcl.size();
+    auto team_time = [&](int t, int g) {
+        double s = 0.0;
+        for (int c : tcl[t]) s += tm(c, g);
+        return s;
+    };
+    int spare = G - std::accumulate(tsize.begin(), tsize.end(), 0);
+    typedef std::pair<double, int> TT;
+    std::priority_queue<TT> heap;
+    for (int t = 0; t < nteam; ++t) heap.push(TT(team_time(t, tsize[t]), t));
+    while (spare > 0 && !heap.empty()) {
+        const TT top = heap.top();
+        heap.pop();
+        const int t = top.second;
+        if (tsize[t] >= max_team) continue;
+        const double t_next = team_time(t, tsize[t] + 1);
+        if (!(t_next < top.first)) continue;  // more groups no longer help
+        tsize[t] += 1;
+        --spare;
+        heap.push(TT(t_next, t));
+    }
+    // longest teams first in the grid
+    std::vector<int> torder(nteam);
+    std::iota(torder.begin(), torder.end(), 0);
+    std::vector<double> tt(nteam);
+    for (int t = 0; t < nteam; ++t) tt[t] = team_time(t, tsize[t]);
+    std::sort(torder.begin(), torder.end(),
+              [&](int p, int q) { return tt[p] > tt[q] || (tt[p] == tt[q] && p < q); });
+
     Plan P;
-    for (int t = 0; t < (int)tcl.size(); ++t) {
-        if (tcl[t].empty()) continue;
+    for (int t : torder) {
         EnsTeam T = {};
         T.size = tsize[t];
         T.cl_begin = (int32_t)P.order.size();
@@ -792,8 +888,8 @@ static Plan plan_teams(const std::vector<int64_t> &sizes, int G, int max_team,
         T.n_max = nmax;
         T.s_max = std::min(EMAXSPLIT, std::max(1, T.size));
         T.scratch_off = P.scratch;
-        P.scratch += 5 * T.size + (nmax + 1) / 2 + 6 * (int64_t)nmax +
-                     (int64_t)T.s_max * 6 * nmax + 8;
+        P.scratch += 64 + 7 * (int64_t)nmax + (int64_t)T.s_max * 6 * nmax +
+                     ((int64_t)T.size * nmax + 1) / 2 + 8;
         const int team_id = (int)P.teams.size();
         P.teams.push_back(T);
         for (int r = 0; r < T.size; ++r) {
@@ -814,13 +910,14 @@ extern "C" int nbody_ensemble_plan(const int64_t *sizes, int32_t n_clusters, int
                                    int32_t *n_teams) {
     if (!sizes || !cfg || !team_of || !team_size || !n_teams || n_clusters < 1 || groups < 1 ||
         !(t_end >= 0.0) || !(cfg->group_rate > 0.0) || !(cfg->steps_coef > 0.0) ||
+        !(cfg->block_coef > 0.0) || !(cfg->tile_us >= 0.0) ||
+        !find_variant(cfg->waves, cfg->j_tile, cfg->i_per_lane) ||
         cfg->max_team < 1)
         return NBODY_E_INVAL;
     std::vector<int64_t> sz(sizes, sizes + n_clusters);
     for (int64_t v : sz)
         if (v < 1) return NBODY_E_INVAL;
-    TimeModel M{cfg->step_us * 1e-6, cfg->barrier_us * 1e-6, cfg->barrier_group_us * 1e-6,
-                cfg->group_rate,     t_end,               cfg->steps_coef, cfg->steps_exp};
+    const TimeModel M = TimeModel::of(*cfg, t_end);
     Plan P = plan_teams(sz, groups, std::min(cfg->max_team, 64), M);
     for (int q = 0; q < (int)P.teams.size(); ++q) {
         const EnsTeam &T = P.teams[q];
@@ -873,8 +970,7 @@ extern "C" int nbody_ensemble_run(nbody_ctx *ctx, const nbody_ensemble *e, doubl
     if (per_cu < 1) return fail(ctx, NBODY_E_DEVICE, "ensemble kernel does not fit a CU");
     const int G = per_cu * ctx->cus;
     const nbody_ensemble_config &cf = ctx->ens_cfg;
-    TimeModel M{cf.step_us * 1e-6,   cf.barrier_us * 1e-6, cf.barrier_group_us * 1e-6,
-                cf.group_rate,       t_end > 0 ? t_end : 0.0, cf.steps_coef, cf.steps_exp};
+    const TimeModel M = TimeModel::of(cf, t_end > 0 ? t_end : 0.0);
     Plan P = plan_teams(sizes, G, std::min(cf.max_team, 64), M);
     const int grid = (int)P.wg_team.size();
     const int nteams = (int)P.teams.size();

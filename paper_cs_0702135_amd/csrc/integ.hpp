@@ -37,13 +37,14 @@ __device__ __forceinline__ void predict_one(double h, const double *x, const dou
 
 // Corrector and new step of one particle.  xp, vp: its predicted position
 // and velocity; a1, k1: the new force and jerk.  State arrays at element q
-// (component stride cs); returns status bits.
+// (component stride cs); returns status bits.  If t_next is given it
+// receives the particle's new t + dt.
 __device__ __forceinline__ int32_t correct_vals(int64_t q, int64_t cs, const double xp[3],
                                                 const double vp[3], const double a1v[3],
                                                 const double k1v[3], double eta, double dt_max,
                                                 double dt_min, int fixed_dt, double *t,
                                                 double *dtv, double *x, double *v, double *a,
-                                                double *k) {
+                                                double *k, double *t_next = nullptr) {
 #pragma clang fp contract(off)
     int32_t st = 0;
     const double h = dtv[q];
@@ -93,6 +94,9 @@ __device__ __forceinline__ int32_t correct_vals(int64_t q, int64_t cs, const dou
             d = dt_min;
         }
         dtv[q] = d;
+        if (t_next) *t_next = t_new + d;
+    } else if (t_next) {
+        *t_next = t_new + h;
     }
     return st;
 }

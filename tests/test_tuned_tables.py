@@ -41,6 +41,7 @@ def test_ensemble_models_are_usable():
         c = json.load(open(f))
         assert c["groups_per_cu"] >= 1 and 1 <= c["max_team"] <= 64
         assert c["group_rate"] > 0 and c["steps_coef"] > 0
+        assert c["tile_us"] >= 0 and c["block_coef"] > 0 and 0 <= c["block_exp"] <= 1
         assert c["step_us"] >= 0 and c["barrier_us"] >= 0 and c["barrier_group_us"] >= 0
         # a workgroup shape the library compiles (autotune.ENS_SHAPES)
         from paper_cs_0702135_amd.autotune import ENS_SHAPES
