@@ -72,6 +72,93 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+COUNTER_RUNS = {
+    # subdirectory of a profiling run -> rocprofv3 counters of that pass
+    "pmc_fetch": "FETCH_SIZE",
+    "pmc_write": "WRITE_SIZE",
+    "pmc_copy_fetch": "FETCH_SIZE",
+    "pmc_copy_write": "WRITE_SIZE",
+    "pmc_f32": "SQ_INSTS_VALU_ADD_F32 SQ_INSTS_VALU_MUL_F32 SQ_INSTS_VALU_FMA_F32 "
+               "SQ_INSTS_VALU_TRANS_F32",
+    "pmc_f64": "SQ_INSTS_VALU_ADD_F64 SQ_INSTS_VALU_MUL_F64 SQ_INSTS_VALU_FMA_F64 "
+               "SQ_INSTS_VALU_CVT",
+    "pmc_flops": "SQ_INSTS_VALU_FLOPS_FP32 SQ_INSTS_VALU SQ_WAVES SQ_BUSY_CYCLES SQ_WAVE_CYCLES "
+                 "SQ_LDS_BANK_CONFLICT SQ_INSTS_LDS GRBM_GUI_ACTIVE",
+}
+
+
+def summarize_counters(run_dir):
+    """Write profiles/force_kernel_traffic.json and force_kernel_valu_mix.json
+    from the rocprofv3 counter passes under run_dir (one subdirectory per
+    pass, named as in COUNTER_RUNS; the pair-kernel passes profile
+    `bench.py --steps 1 --warmup 0 --no-cpu --no-aux`, the copy passes
+    `bench.py --calib-copy`).  The values are those of the last pair-kernel
+    dispatch of each pass (the timed block-step launch); FETCH_SIZE and
+    WRITE_SIZE are in KiB and are scaled by what they read for the 1 GiB copy."""
+    import csv
+
+    def read(sub, kernel_prefix):
+        out = {}
+        with open(os.path.join(run_dir, sub, "run_counter_collection.csv")) as f:
+            for r in csv.DictReader(f):
+                if r["Kernel_Name"].startswith(kernel_prefix):
+                    # later dispatches overwrite earlier ones
+                    out.setdefault(r["Counter_Name"], {})[int(r["Dispatch_Id"])] = \
+                        float(r["Counter_Value"])
+        return {k: [v[d] for d in sorted(v)] for k, v in out.items()}
+
+    def cmd(sub, prog):
+        return ("rocprofv3 --pmc %s --output-format csv -d %s -o run -- python3 bench.py %s"
+                % (COUNTER_RUNS[sub], os.path.join(run_dir, sub), prog))
+
+    pair = "void nb::force_kernel<0, 2, 2, 0>"
+    prog = "--steps 1 --warmup 0 --no-cpu --no-aux"
+    copy_bytes = float(1 << 30)
+    fetch = read("pmc_fetch", pair)["FETCH_SIZE"]
+    write = read("pmc_write", pair)["WRITE_SIZE"]
+    cf = read("pmc_copy_fetch", "__amd_rocclr_copyBuffer")["FETCH_SIZE"]
+    cw = read("pmc_copy_write", "__amd_rocclr_copyBuffer")["WRITE_SIZE"]
+    fetch_factor = copy_bytes / (max(cf) * 1024.0)
+    write_factor = copy_bytes / (max(cw) * 1024.0)
+    traffic = {
+        "kernel": pair + "(nb::KArgs)",
+        "workload": "plummer N=2^20 shared block step (bench.py), block-step launch (the timed kind)",
+        "fetch_kib": fetch, "write_kib": write,
+        "fetch_factor": fetch_factor, "write_factor": write_factor,
+        "bytes_per_launch": (fetch[-1] * fetch_factor + write[-1] * write_factor) * 1024.0,
+        "source_sha256": kernel_source_digest(),
+        "commands": [cmd("pmc_fetch", prog), cmd("pmc_write", prog),
+                     "calibration: " + cmd("pmc_copy_fetch", "--calib-copy") + " ; "
+                     + cmd("pmc_copy_write", "--calib-copy")
+                     + " (1 GiB device copy: FETCH_SIZE %.0f KiB, WRITE_SIZE %.0f KiB)"
+                     % (max(cf), max(cw))],
+    }
+    counters = {}
+    for sub in ("pmc_f32", "pmc_f64", "pmc_flops"):
+        for k, v in read(sub, pair).items():
+            counters[k] = v[-1]
+    inter = float(1 << 20) * ((1 << 20) - 1)
+    ex = 64.0 * counters["SQ_INSTS_VALU_FLOPS_FP32"] / inter
+    mix = {
+        "kernel": pair + "(nb::KArgs)",
+        "workload": "plummer N=2^20 shared block step (bench.py), block-step launch",
+        "counters_per_launch": counters,
+        "executed_f32_flops_per_interaction": round(ex, 3),
+        "valu_instructions_per_interaction": round(64.0 * counters["SQ_INSTS_VALU"] / inter, 3),
+        "source_sha256": kernel_source_digest(),
+        "commands": [cmd(sub, prog) for sub in ("pmc_f32", "pmc_f64", "pmc_flops")],
+    }
+    for name, obj in (("force_kernel_traffic.json", traffic),
+                      ("force_kernel_valu_mix.json", mix)):
+        with open(os.path.join(ROOT, "profiles", name), "w") as f:
+            json.dump(obj, f, indent=1)
+            f.write("\n")
+    print(json.dumps({"bytes_per_launch": traffic["bytes_per_launch"],
+                      "executed_f32_flops_per_interaction": mix["executed_f32_flops_per_interaction"],
+                      "valu_instructions_per_interaction":
+                          mix["valu_instructions_per_interaction"]}))
+
+
 def fit_power_law(x, y):
     """Least-squares fit of y = c x^p in log-log space; returns (c, p)."""
     import numpy as np
@@ -369,7 +456,14 @@ def main():
                     help="largest N of the results-table protocol")
     ap.add_argument("--calib-copy", action="store_true",
                     help="only run one plain device copy of 1 GiB (HBM-counter calibration)")
+    ap.add_argument("--summarize-counters", metavar="RUN_DIR",
+                    help="write the pair kernel's traffic and instruction-mix summaries under "
+                         "profiles/ from the counter passes in RUN_DIR (no GPU)")
     args = ap.parse_args()
+
+    if args.summarize_counters:
+        summarize_counters(args.summarize_counters)
+        return
 
     if args.calib_copy:
         import torch
