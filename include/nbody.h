@@ -57,11 +57,11 @@ extern "C" {
  *                   terms (rsqrt on the VALU) summed in float32 over at most
  *                   8 tiles of consecutive j, those sums added in float64;
  *   NBODY_ACC_DS    the compensated (accurate) mode.  nbody_force,
- *                   nbody_init / nbody_blockstep and nbody_shared_run
- *                   evaluate the pair terms in float64 (s^(-1/2) from the
- *                   float32 estimate refined by a float64 Newton step) with
- *                   float64 sums; the ensemble and the adjoint keep float32
- *                   pair terms and fold their tile sums by TwoSum into
+ *                   nbody_init / nbody_blockstep, nbody_shared_run and
+ *                   nbody_ensemble_run evaluate the pair terms in float64
+ *                   (s^(-1/2) from the float32 estimate refined by a float64
+ *                   Newton step) with float64 sums; the adjoint keeps float32
+ *                   pair terms and folds its tile sums by TwoSum into
  *                   float-float sums. */
 #define NBODY_ACC_FP32 0u
 #define NBODY_ACC_DS 1u

@@ -56,7 +56,8 @@ constexpr int EMAXSPLIT = 64;    // largest j split of a team's pair pass
 struct EnsCluster {
     int64_t off;
     int32_t n;
-    float eps2;
+    float eps2;    // softening^2 for the float32 pair terms
+    double eps2d;  // and for the float64 pair terms of the compensated mode
 };
 
 struct EnsTeam {
@@ -85,7 +86,7 @@ struct EnsArgs {
 struct TileRec {
     double x, y, z, u, v, w;
     float m, pad;
-    double pad2;
+    double md;  // the mass in float64 (compensated mode)
 };
 
 __device__ __forceinline__ bool aborted(const int32_t *abort) {
@@ -146,17 +147,6 @@ __device__ bool team_barrier(uint32_t *flags, int g, int rank, uint32_t &epoch, 
     return ok != 0;
 }
 
-__device__ __forceinline__ void ds_fold(float &hi, float &lo, float x, bool ds) {
-    if (ds) {
-        const float s = hi + x;
-        const float bp = s - hi;
-        lo += (hi - (s - bp)) + (x - bp);
-        hi = s;
-    } else {
-        hi += x;
-    }
-}
-
 // Members of an active block, ascending: every group of a team compacts
 // the whole cluster into its own copy act[0..n_i) (block slot s is particle
 // act[s]).  A null act stands for the whole cluster in index order.
@@ -171,7 +161,7 @@ __device__ __forceinline__ int block_member(const Block &B, int s) {
 // State of one particle as loaded, before prediction.
 struct Raw {
     double t, x[3], v[3], a[3], k[3];
-    float m;
+    double m;
 };
 
 template <bool PRED>
@@ -187,7 +177,7 @@ __device__ __forceinline__ void load_raw(const EnsArgs &A, int64_t q, Raw &r) {
         }
     }
     if (PRED) r.t = A.t[q];
-    r.m = (float)A.m[q];
+    r.m = A.m[q];
 }
 
 // Position and velocity predicted to tn (PRED) or as stored.
@@ -230,12 +220,17 @@ __device__ __forceinline__ double group_min(double v, double *smin) {
 // it is masked by index only for eps2 < 1e-12.  (Holding the next j tile
 // in registers while the current one is summed would cost the third group
 // per CU its registers; the co-resident groups hide the tile loads.)
+// Float32 mode (DS false): float32 pair terms of float64-formed relative
+// coordinates, summed in float32 per tile and over the item's tiles.
+// Compensated mode (DS true): float64 pair terms (s^-1/2 from the float32
+// estimate and one float64 Newton step) summed in float64.
 constexpr float EMASK = 1e-12f;  // below this eps2 the self pair is masked
 
 template <class Sh, bool DS, bool PRED, int NI, int L>
-__device__ void ens_pair_item(const EnsArgs &A, int64_t base, float eps2, double tn,
-                              const Block &B, int n_i, int slot0, int j0, int j1, TileRec *tile,
-                              double (*red)[6 * Sh::IT][64], double (&tot)[Sh::IT][6]) {
+__device__ void ens_pair_item(const EnsArgs &A, int64_t base, float eps2, double eps2d,
+                              double tn, const Block &B, int n_i, int slot0, int j0, int j1,
+                              TileRec *tile, double (*red)[6 * Sh::IT][64],
+                              double (&tot)[Sh::IT][6]) {
     constexpr int SPL = 64 / L;
     const int tid = threadIdx.x;
     const int lane = tid & 63;
@@ -269,11 +264,15 @@ __device__ void ens_pair_item(const EnsArgs &A, int64_t base, float eps2, double
             hi = max(hi, __shfl_xor(hi, o, 64));
         }
     }
-    float sh[NI][6], sl[NI][6];
+    float sh[NI][6];   // float32 mode: running sums over the item's tiles
+    double sd[NI][6];  // compensated mode: float64 sums
 #pragma unroll
     for (int t = 0; t < NI; ++t)
 #pragma unroll
-        for (int c = 0; c < 6; ++c) sh[t][c] = sl[t][c] = 0.0f;
+        for (int c = 0; c < 6; ++c) {
+            sh[t][c] = 0.0f;
+            sd[t][c] = 0.0;
+        }
     constexpr int PER = Sh::TILE / Sh::W;  // tile records per wave
     for (int jt = j0; jt < j1; jt += Sh::TILE) {
         const int cnt = min(Sh::TILE, j1 - jt);
@@ -290,7 +289,8 @@ __device__ void ens_pair_item(const EnsArgs &A, int64_t base, float eps2, double
             R.u = pv[0];
             R.v = pv[1];
             R.w = pv[2];
-            R.m = nxt.m;
+            R.m = (float)nxt.m;
+            R.md = nxt.m;
             tile[q] = R;
         }
         __syncthreads();
@@ -300,6 +300,34 @@ __device__ void ens_pair_item(const EnsArgs &A, int64_t base, float eps2, double
         for (int t = 0; t < NI; ++t)
 #pragma unroll
             for (int c = 0; c < 6; ++c) in[t][c] = 0.0f;
+        auto body64 = [&](const TileRec &R, const int j, const bool mask)
+            __attribute__((always_inline)) {
+#pragma unroll
+            for (int t = 0; t < NI; ++t) {
+                const double dx = R.x - xi[t], dy = R.y - yi[t], dz = R.z - zi[t];
+                const double du = R.u - ui[t], dv = R.v - vi[t], dw = R.w - wi[t];
+                double s2 = fma(dz, dz, fma(dy, dy, fma(dx, dx, eps2d)));
+                double mj = R.md;
+                if (mask) {
+                    const bool self = (j == ip[t]);
+                    s2 = self ? 1.0 : s2;
+                    mj = self ? 0.0 : mj;
+                }
+                const double rv = fma(dz, dw, fma(dy, dv, dx * du));
+                const double y0 = (double)__builtin_amdgcn_rsqf((float)s2);
+                const double e = fma(-(s2 * y0), y0, 1.0);
+                const double y = fma(0.5 * y0, e, y0);
+                const double y2 = y * y;
+                const double mr3 = (mj * y) * y2;
+                const double w3 = (rv * y2) * -3.0;
+                sd[t][0] = fma(mr3, dx, sd[t][0]);
+                sd[t][1] = fma(mr3, dy, sd[t][1]);
+                sd[t][2] = fma(mr3, dz, sd[t][2]);
+                sd[t][3] = fma(mr3, fma(w3, dx, du), sd[t][3]);
+                sd[t][4] = fma(mr3, fma(w3, dy, dv), sd[t][4]);
+                sd[t][5] = fma(mr3, fma(w3, dz, dw), sd[t][5]);
+            }
+        };
         auto body = [&](const TileRec &R, const int j, const bool mask)
             __attribute__((always_inline)) {
 #pragma unroll
@@ -328,22 +356,31 @@ __device__ void ens_pair_item(const EnsArgs &A, int64_t base, float eps2, double
                 in[t][5] = fmaf(mr3, fmaf(w3, dz, dw), in[t][5]);
             }
         };
-        if (maskable && (jt + r0 <= hi) && (jt + r1 > lo)) {
-            for (int r = r0 + ph; r < r1; r += L) body(tile[r], jt + r, true);
+        if constexpr (DS) {
+            if (maskable && (jt + r0 <= hi) && (jt + r1 > lo)) {
+                for (int r = r0 + ph; r < r1; r += L) body64(tile[r], jt + r, true);
+            } else {
+#pragma unroll 2
+                for (int r = r0 + ph; r < r1; r += L) body64(tile[r], jt + r, false);
+            }
         } else {
+            if (maskable && (jt + r0 <= hi) && (jt + r1 > lo)) {
+                for (int r = r0 + ph; r < r1; r += L) body(tile[r], jt + r, true);
+            } else {
 #pragma unroll 4
-            for (int r = r0 + ph; r < r1; r += L) body(tile[r], jt + r, false);
+                for (int r = r0 + ph; r < r1; r += L) body(tile[r], jt + r, false);
+            }
+#pragma unroll
+            for (int t = 0; t < NI; ++t)
+#pragma unroll
+                for (int c = 0; c < 6; ++c) sh[t][c] += in[t][c];
         }
-#pragma unroll
-        for (int t = 0; t < NI; ++t)
-#pragma unroll
-            for (int c = 0; c < 6; ++c) ds_fold(sh[t][c], sl[t][c], in[t][c], DS);
     }
 #pragma unroll
     for (int t = 0; t < NI; ++t)
 #pragma unroll
         for (int c = 0; c < 6; ++c) {
-            double s = (double)sh[t][c] + (double)sl[t][c];
+            double s = DS ? sd[t][c] : (double)sh[t][c];
 #pragma unroll
             for (int o = 1; o < L; o <<= 1) s += __shfl_xor(s, o, 64);
             tot[t][c] = s;
@@ -402,7 +439,8 @@ __device__ __forceinline__ int ens_splits(int n_i, int n, int g, int s_max) {
 // n_max), otherwise its split's partial sums to part; share_sums adds the S
 // partials of a slot in split order once the team has passed a barrier.
 template <class Sh, bool DS, bool PRED>
-__device__ void ens_pairs(const EnsArgs &A, int64_t base, int n, float eps2, double tn,
+__device__ void ens_pairs(const EnsArgs &A, int64_t base, int n, float eps2, double eps2d,
+                          double tn,
                           const Block &B, int n_i, int g, int rank, int S, int n_max,
                           double *anew, double *knew, double *part, TileRec *tile,
                           double (*red)[6 * Sh::IT][64]) {
@@ -419,22 +457,22 @@ __device__ void ens_pairs(const EnsArgs &A, int64_t base, int n, float eps2, dou
         double tot[Sh::IT][6];
         int ni = 1, L = 1;
         if (Sh::IT == 2 && w == 128) {
-            ens_pair_item<Sh, DS, PRED, Sh::IT, 1>(A, base, eps2, tn, B, n_i, slot0, j0, j1,
+            ens_pair_item<Sh, DS, PRED, Sh::IT, 1>(A, base, eps2, eps2d, tn, B, n_i, slot0, j0, j1,
                                                    tile, red, tot);
             ni = 2;
         } else if (w == 64) {
-            ens_pair_item<Sh, DS, PRED, 1, 1>(A, base, eps2, tn, B, n_i, slot0, j0, j1, tile, red,
+            ens_pair_item<Sh, DS, PRED, 1, 1>(A, base, eps2, eps2d, tn, B, n_i, slot0, j0, j1, tile, red,
                                               tot);
         } else if (PRED && w == 32) {
-            ens_pair_item<Sh, DS, PRED, 1, 2>(A, base, eps2, tn, B, n_i, slot0, j0, j1, tile, red,
+            ens_pair_item<Sh, DS, PRED, 1, 2>(A, base, eps2, eps2d, tn, B, n_i, slot0, j0, j1, tile, red,
                                               tot);
             L = 2;
         } else if (PRED && w == 16) {
-            ens_pair_item<Sh, DS, PRED, 1, 4>(A, base, eps2, tn, B, n_i, slot0, j0, j1, tile, red,
+            ens_pair_item<Sh, DS, PRED, 1, 4>(A, base, eps2, eps2d, tn, B, n_i, slot0, j0, j1, tile, red,
                                               tot);
             L = 4;
         } else if (PRED) {
-            ens_pair_item<Sh, DS, PRED, 1, 8>(A, base, eps2, tn, B, n_i, slot0, j0, j1, tile, red,
+            ens_pair_item<Sh, DS, PRED, 1, 8>(A, base, eps2, eps2d, tn, B, n_i, slot0, j0, j1, tile, red,
                                               tot);
             L = 8;
         }
@@ -545,12 +583,13 @@ __global__ __launch_bounds__(Sh::TH, 3) void ensemble_kernel(const EnsArgs A) {
         const int64_t base = C.off;
         const int n = C.n;
         const float eps2 = C.eps2;
+        const double eps2d = C.eps2d;
         if (rank == 0 && tid == 0) A.clock[2 * c] = wall_clock64();
 
         // ---- initialisation: pair sums of every particle, initial steps
         {
             const int S = ens_splits<Sh>(n, n, g, T.s_max);
-            ens_pairs<Sh, DS, false>(A, base, n, eps2, 0.0, Block{nullptr}, n, g, rank, S,
+            ens_pairs<Sh, DS, false>(A, base, n, eps2, eps2d, 0.0, Block{nullptr}, n, g, rank, S,
                                      n_max, anew, knew, part, tile, red);
             if (!team_barrier(bar, g, rank, epoch, A.abort, A.spin_limit)) return;
             const int per = (n + g - 1) / g;
@@ -633,7 +672,8 @@ __global__ __launch_bounds__(Sh::TH, 3) void ensemble_kernel(const EnsArgs A) {
             }
             rest = group_min<Sh>(rmin, smin);
             const int S = ens_splits<Sh>(n_i, n, g, T.s_max);
-            ens_pairs<Sh, DS, true>(A, base, n, eps2, tn, Block{act}, n_i, g, rank, S, n_max,
+            ens_pairs<Sh, DS, true>(A, base, n, eps2, eps2d, tn, Block{act}, n_i, g, rank, S,
+                                    n_max,
                                     anew, knew, part, tile, red);
             if (!team_barrier(bar, g, rank, epoch, A.abort, A.spin_limit)) return;
 
@@ -976,7 +1016,8 @@ extern "C" int nbody_ensemble_run(nbody_ctx *ctx, const nbody_ensemble *e, doubl
     const int nteams = (int)P.teams.size();
 
     std::vector<EnsCluster> hc(nc);
-    for (int c = 0; c < nc; ++c) hc[c] = EnsCluster{e->offsets[c], (int32_t)sizes[c], (float)e->eps2[c]};
+    for (int c = 0; c < nc; ++c)
+        hc[c] = EnsCluster{e->offsets[c], (int32_t)sizes[c], (float)e->eps2[c], e->eps2[c]};
 
     // one device block: tables, counters, team scratch
     auto al = [](size_t b) { return (b + 255) & ~size_t(255); };
