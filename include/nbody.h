@@ -355,8 +355,11 @@ int nbody_ensemble_info(nbody_ctx *ctx, int32_t *grid, int32_t *teams);
  *   model_seconds : HOST float64[n_clusters] output (may be NULL), modelled
  *                   time of each cluster on its team.
  *   n_teams       : HOST output.
+ * Clusters that share a team (several clusters on one single-group team)
+ * run one after the other; the team's time is the sum of theirs.
  * Returns NBODY_E_INVAL on null pointers, n_clusters < 1, groups < 1, a
- * cluster size < 1 or a model with non-positive rates. */
+ * cluster size < 1, a model with non-positive rates or a workgroup shape
+ * that is not compiled. */
 int nbody_ensemble_plan(const int64_t *sizes, int32_t n_clusters, int32_t groups,
                         const nbody_ensemble_config *cfg, double t_end, int32_t *team_of,
                         int32_t *team_size, double *model_seconds, int32_t *n_teams);
