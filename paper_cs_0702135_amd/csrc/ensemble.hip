@@ -791,10 +791,12 @@ struct TimeModel {
     double pass(double n_i, double n, int g) const {
         return tiles((int64_t)std::ceil(n_i), (int64_t)n, g) * tile_s + n_i * n / ((double)g * rate);
     }
-    double time(double n, int g) const {
-        return pass(n, n, g) + steps(n) * (step_s + (g > 1 ? barrier_s + barrier_g_s * g : 0.0) +
-                                           pass(block(n), n, g));
+    // time of a cluster of n particles with `st` steps of blocks of `blk`
+    double time_sb(double n, double st, double blk, int g) const {
+        return pass(n, n, g) + st * (step_s + (g > 1 ? barrier_s + barrier_g_s * g : 0.0) +
+                                     pass(blk, n, g));
     }
+    double time(double n, int g) const { return time_sb(n, steps(n), block(n), g); }
     static TimeModel of(const nbody_ensemble_config &c, double t_end) {
         return TimeModel{c.step_us * 1e-6,  c.barrier_us * 1e-6, c.barrier_group_us * 1e-6,
                          c.group_rate,      t_end,              c.steps_coef,
@@ -806,19 +808,22 @@ struct TimeModel {
 // Team plan of least modelled makespan.  For a target time T every cluster
 // needs the fewest groups g(T) whose modelled time is within T; the clusters
 // that one group finishes within T are packed onto shared single-group teams
-// (first fit, longest first: a team runs its clusters one after the other),
+// (longest first onto the least-loaded one: a team runs its clusters one
+// after the other),
 // the others get teams of g(T) groups.  T is bisected down to the least
 // value whose plan fits the grid; the groups left over then go, one at a
 // time, to the team with the longest modelled time while that shortens it.
 static Plan plan_teams(const std::vector<int64_t> &sizes, int G, int max_team,
                        const TimeModel &M) {
     const int nc = (int)sizes.size();
-    // modelled time of every cluster on 1 .. max_team groups
-    std::vector<double> tab((size_t)nc * max_team);
-    for (int c = 0; c < nc; ++c)
-        for (int g = 1; g <= max_team; ++g)
-            tab[(size_t)c * max_team + g - 1] = M.time((double)sizes[c], g);
-    auto tm = [&](int c, int g) { return tab[(size_t)c * max_team + g - 1]; };
+    // modelled time of cluster c on g groups (its step count and block size
+    // computed once)
+    std::vector<double> st(nc), blk(nc);
+    for (int c = 0; c < nc; ++c) {
+        st[c] = M.steps((double)sizes[c]);
+        blk[c] = M.block((double)sizes[c]);
+    }
+    auto tm = [&](int c, int g) { return M.time_sb((double)sizes[c], st[c], blk[c], g); };
     std::vector<double> t1(nc);
     double lo = 0.0, hi = 0.0;
     for (int c = 0; c < nc; ++c) {
@@ -850,17 +855,25 @@ static Plan plan_teams(const std::vector<int64_t> &sizes, int G, int max_team,
             gsz[c] = g;
             used += g;
         }
+        // longest first onto the least-loaded shared team, a new one when
+        // even that would pass T (O(log teams) per cluster)
+        typedef std::pair<double, int> LB;
+        std::priority_queue<LB, std::vector<LB>, std::greater<LB>> least;
         for (int c : by_t1) {
             if (gsz[c] != 0) continue;
             gsz[c] = 1;
-            size_t b = 0;
-            while (b < bins.size() && bin_load[b] + t1[c] > T) ++b;
-            if (b == bins.size()) {
+            int b;
+            if (!least.empty() && least.top().first + t1[c] <= T) {
+                b = least.top().second;
+                least.pop();
+            } else {
+                b = (int)bins.size();
                 bins.push_back({});
                 bin_load.push_back(0.0);
             }
             bins[b].push_back(c);
             bin_load[b] += t1[c];
+            least.push(LB(bin_load[b], b));
         }
         return used + (int64_t)bins.size();
     };
