@@ -5,9 +5,10 @@
 // particle are added in float32 in ascending order of the pair-acceleration
 // magnitude m_j |r| s^(-3/2) (ties by j), all seven sums in that one order.
 //
-// One workgroup per active particle: its n_j - 1 keys (float64) and j
-// indices are sorted in LDS by a bitonic network, then the sorted terms are
-// evaluated 256 at a time into LDS and seven lanes add one component each
+// One 1024-thread workgroup per active particle (16 waves, so that the LDS
+// latency of the sort is hidden): its n_j - 1 keys (float64) and j indices
+// are sorted in LDS by a bitonic network, then the sorted terms are
+// evaluated 1024 at a time into LDS and seven lanes add one component each
 // in sorted order.  The float64 expressions are evaluated without
 // contraction, in the order they are written, so that the rounding of each
 // term and key is the plain IEEE rounding of that expression.
@@ -19,7 +20,7 @@
 namespace nb {
 
 constexpr int kSortMax = 8192;     // largest n_j (LDS: 8 + 2 bytes per j)
-constexpr int kSortThreads = 256;
+constexpr int kSortThreads = 1024;
 constexpr uint16_t kInvalid = 0xFFFF;  // the self pair and the padding
 
 struct PairTerms {
@@ -102,8 +103,8 @@ __global__ __launch_bounds__(kSortThreads) void force_sorted_kernel(
                 __syncthreads();
             }
         }
-        // the n_j - 1 terms in sorted order, 256 at a time; lane c < 7 adds
-        // component c in float32
+        // the n_j - 1 terms in sorted order, a workgroup's worth at a time;
+        // lane c < 7 adds component c in float32
         const int m = n_j - 1;
         float sum = 0.0f;
         for (int base = 0; base < m; base += kSortThreads) {
