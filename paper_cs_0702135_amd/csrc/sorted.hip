@@ -51,7 +51,11 @@ __global__ __launch_bounds__(kSortThreads) void force_sorted_kernel(
 #pragma clang fp contract(off)
     __shared__ double key[kSortMax];
     __shared__ uint16_t idx[kSortMax];
-    __shared__ float term[7][kSortThreads];
+    // rows padded by four floats: rows stay 16-byte aligned for the summing
+    // lanes' 4-float reads, and the seven lanes' reads of one column fall in
+    // different banks
+    constexpr int kRow = kSortThreads + 4;
+    __shared__ __attribute__((aligned(16))) float term[7][kRow];
     const int tid = threadIdx.x;
     int n_pad = 1;
     while (n_pad < n_j) n_pad <<= 1;
@@ -80,24 +84,22 @@ __global__ __launch_bounds__(kSortThreads) void force_sorted_kernel(
             idx[j] = id;
         }
         __syncthreads();
-        // bitonic sort, ascending by (valid first, key, j)
+        // bitonic sort, ascending by (valid first, key, j); each thread takes
+        // whole compare-exchange pairs (t, t + jj), t with a zero jj bit
         for (int kk = 2; kk <= n_pad; kk <<= 1) {
             for (int jj = kk >> 1; jj > 0; jj >>= 1) {
-                for (int t = tid; t < n_pad; t += kSortThreads) {
-                    const int p = t ^ jj;
-                    if (p > t) {
-                        const bool it = idx[t] == kInvalid, ip = idx[p] == kInvalid;
-                        const bool gt = it != ip ? it
-                                                 : (key[t] > key[p] ||
-                                                    (key[t] == key[p] && idx[t] > idx[p]));
-                        if (gt == ((t & kk) == 0)) {
-                            const double kt = key[t];
-                            key[t] = key[p];
-                            key[p] = kt;
-                            const uint16_t xt = idx[t];
-                            idx[t] = idx[p];
-                            idx[p] = xt;
-                        }
+                for (int c = tid; c < (n_pad >> 1); c += kSortThreads) {
+                    const int t = ((c & ~(jj - 1)) << 1) | (c & (jj - 1));
+                    const int p = t | jj;
+                    const double kt = key[t], kp = key[p];
+                    const uint16_t xt = idx[t], xp = idx[p];
+                    const bool it = xt == kInvalid, ip = xp == kInvalid;
+                    const bool gt = it != ip ? it : (kt > kp || (kt == kp && xt > xp));
+                    if (gt == ((t & kk) == 0)) {
+                        key[t] = kp;
+                        key[p] = kt;
+                        idx[t] = xp;
+                        idx[p] = xt;
                     }
                 }
                 __syncthreads();
@@ -128,7 +130,17 @@ __global__ __launch_bounds__(kSortThreads) void force_sorted_kernel(
             __syncthreads();
             if (tid < 7) {
                 const int cnt = min(kSortThreads, m - base);
-                for (int q = 0; q < cnt; ++q) sum = sum + term[tid][q];
+                const float4 *row = reinterpret_cast<const float4 *>(&term[tid][0]);
+                int q = 0;
+#pragma unroll 8
+                for (; q + 4 <= cnt; q += 4) {
+                    const float4 v = row[q >> 2];
+                    sum = sum + v.x;
+                    sum = sum + v.y;
+                    sum = sum + v.z;
+                    sum = sum + v.w;
+                }
+                for (; q < cnt; ++q) sum = sum + term[tid][q];
             }
             __syncthreads();
         }
