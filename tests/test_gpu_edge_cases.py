@@ -69,6 +69,35 @@ def test_kepler_binary_blockstep_and_ensemble_eps0(orc):
     assert np.abs(host(out["x"])[:, :2] - s.x).max() < 5e-8
 
 
+@pytest.mark.parametrize("mode", ["fp32", "ds"])
+def test_masked_self_pair_eps0_both_modes(orc, mode):
+    # eps = 0: the self pair must be masked by index (s = 0 otherwise), in
+    # the driver's pair kernels and in the ensemble's float32 and float64
+    # pair bodies; the compensated mode follows the float64 oracle closely
+    need_gpu()
+    import paper_cs_0702135_amd as nb
+    pos, vel, m, om = _binary()
+    t_end, dt_max = 0.5, 0.125
+    s = orc.init_state(pos, vel, m, 0.0, dt_max=dt_max)
+    r_steps, _ = orc.integrate(s, t_end)
+    tol = {"fp32": 5e-8, "ds": 1e-11}[mode]
+    sysg = nb.System(dev(pos), dev(vel), dev(m), 0.0, dt_max=dt_max, mode=mode)
+    g_steps = sysg.run(t_end)
+    dx_drv = np.abs(host(sysg.x) - s.x).max()
+    p2, v2, m2 = plummer(100, 7)
+    P = np.concatenate([pos, p2], axis=1)
+    V = np.concatenate([vel, v2], axis=1)
+    M = np.concatenate([m, m2])
+    off = np.array([0, 2, 102], dtype=np.int64)
+    out = nb.ensemble_run(dev(P), dev(V), dev(M), off, np.array([0.0, 1e-4]), t_end,
+                          dt_max=dt_max, mode=mode)
+    dx_ens = np.abs(host(out["x"])[:, :2] - s.x).max()
+    say("eps=0 binary %s: steps driver %d ensemble %d oracle %d, |dx| driver %.2e ensemble %.2e"
+        % (mode, g_steps, out["steps"][0], r_steps, dx_drv, dx_ens))
+    assert abs(g_steps - r_steps) <= 1 and abs(out["steps"][0] - r_steps) <= 1
+    assert dx_drv < tol and dx_ens < tol
+
+
 def test_single_particle_and_empty_active_set():
     need_gpu()
     import paper_cs_0702135_amd as nb
