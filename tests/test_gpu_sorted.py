@@ -68,6 +68,18 @@ def test_sorted_unequal_masses_and_ties(orc):
     assert np.array_equal(a, ra) and np.array_equal(k, rk) and np.array_equal(p, rp)
 
 
+def test_sorted_out_of_range_index_is_reported():
+    need_gpu()
+    import paper_cs_0702135_amd as nb
+    import torch
+    pos, vel, m = plummer(300, 9)
+    bad = torch.tensor([5, 300, 8], dtype=torch.int32, device="cuda")
+    nb.force_sorted(dev(pos), dev(vel), dev(m), 1e-4, bad)
+    with pytest.raises(nb.NBodyError):
+        nb.context().sync_status()
+    nb.context().sync_status()  # cleared once reported
+
+
 def test_sorted_rejects_large_n():
     need_gpu()
     import paper_cs_0702135_amd as nb
