@@ -8,22 +8,22 @@
 // of a block step (block selection and pair sums; split reduction and
 // correction) are spread over the team's groups and each is closed by a team
 // barrier (one arrival word per group in global memory, agent-scope
-// release/acquire).  Barrier
-// waits are bounded by a wall-clock limit: if one expires the launch raises
-// an abort flag that every group checks, so the grid always drains.
+// release/acquire).  Barrier waits are bounded by a wall-clock limit: if one
+// expires the launch raises an abort flag that every group checks, so the
+// grid always drains.
 //
 // The host plans the teams from a time model.  A cluster of N particles
-// takes about S = c N^p t_end block steps with blocks of 0.20 N^0.81
-// particles (the paper fits c = 247, p = 0.35 for the steps per time unit,
-// and that block size; c and p are recalibrated from measured runs), so on a
-// team of g groups it takes
-//     T(N, g) = S (step + [g > 1] (b0 + b1 g) + 0.20 N^1.81 / (g rate))
-// where step is the fixed latency of one block step on one group, b0 + b1 g
-// the extra cost of a step of a team of g groups and rate the pair
-// interactions per second of one group (all calibrated by the autotuner).
-// The plan minimises the modelled makespan: clusters that one group
-// finishes in time share single-group teams, the others get the fewest
-// groups that finish them in time, and spare groups go to the slowest teams.
+// takes about S = c N^p t_end block steps with blocks of B = b N^q particles
+// (the paper's Section 5 fits, c = 247, p = 0.35, b = 0.20, q = 0.81, are the
+// defaults; the autotuner can refit them), so on a team of g groups it takes
+//     T(N, g) = P(N) + S (step + [g > 1] (b0 + b1 g) + P(B))
+// where P(n_i) is the busiest group's share of a pair pass over n_i
+// particles (its j tiles times a tile latency plus n_i N / (g rate)), step
+// the fixed latency of one block step on one group and b0 + b1 g the extra
+// cost of a step of a team of g groups.  The plan minimises the modelled
+// makespan: clusters that one group finishes in time share single-group
+// teams, the others get the fewest groups that finish them in time, and
+// spare groups go to the slowest teams.
 //
 // The j particles of a pair-sum pass are staged through LDS in tiles (the
 // state is rewritten during this launch, so it cannot be read through the
