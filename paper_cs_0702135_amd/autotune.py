@@ -11,7 +11,15 @@ accumulation mode.
 Candidates use the float64-difference coordinate form (rep 0); the
 float-float form (rep 1) measured slower on gfx950 and is only tried with
 `forms=(0, 1)`; the float32-velocity form (rep 2) changes the jerk's
-accuracy and is only tried when asked for explicitly.
+accuracy and is only tried when asked for explicitly.  Small blocks also try
+the j-lane layout (layout 1: one j per lane, a few wave-uniform i), and the
+table's small-block entry is what the block-step driver launches beside its
+i-lane kernel.
+
+The ensemble (nbody_ensemble_run) is calibrated separately
+(calibrate_ensemble): every compiled workgroup shape at two occupancies on a
+representative launch, with its team-planning model refitted on the measured
+per-cluster times, keeping the fastest measured launch.
 """
 from __future__ import annotations
 
