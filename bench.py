@@ -299,6 +299,43 @@ def small_block_sweep(P, V, M, eps2, cfg, reps=20):
     return small
 
 
+def plummer64k_run(mode):
+    """Plummer N = 65536, eps = 1/1024, built-in launch shapes: the full-N
+    force-only throughput, then the block-step run to t = 1/8 (wall time,
+    steps, energy drift)."""
+    import torch
+
+    import paper_cs_0702135_amd as nb
+    from workloads.plummer import CONFIGS, plummer
+    c2 = CONFIGS["plummer64k"]
+    p2, v2, m2 = (torch.from_numpy(a).cuda() for a in plummer(c2.n, c2.seed))
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    out = {}
+    nb.force(p2, v2, m2, c2.eps2, None, mode)
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(5):
+        nb.force(p2, v2, m2, c2.eps2, None, mode)
+    e1.record()
+    torch.cuda.synchronize()
+    out["plummer64k_force_only_interactions_per_s"] = 5 * c2.n * (c2.n - 1.0) / (
+        e0.elapsed_time(e1) * 1e-3)
+    s2 = nb.System(p2, v2, m2, c2.eps2, eta=c2.eta, dt_max=c2.dt_max, mode=mode)
+    e_0 = s2.energy()
+    torch.cuda.synchronize()
+    ta = time.perf_counter()
+    steps2 = s2.run(c2.t_end)
+    torch.cuda.synchronize()
+    tb = time.perf_counter()
+    e_1 = s2.energy()
+    out["plummer64k_run_seconds"] = tb - ta
+    out["plummer64k_block_steps"] = steps2
+    out["plummer64k_run_interactions_per_s"] = s2.interactions / (tb - ta)
+    out["plummer64k_energy_drift_per_time_unit"] = abs((e_1 - e_0) / e_0) / c2.t_end
+    log("plummer64k: %d block steps in %.4f s" % (steps2, tb - ta))
+    return out
+
+
 def small_blocks_only(args):
     """Only the small-block sweep at N = 2^20 (the tuned table installed as
     the default run installs it); one JSON line."""
@@ -452,6 +489,8 @@ def main():
                     help="run only the batched-ensemble workload")
     ap.add_argument("--small-blocks", action="store_true",
                     help="run only the small-block pair-sum sweep at N = 2^20")
+    ap.add_argument("--plummer64k", action="store_true",
+                    help="run only the Plummer N = 65536 block-step run to t = 1/8")
     ap.add_argument("--table-max-n", type=int, default=1 << 19,
                     help="largest N of the results-table protocol")
     ap.add_argument("--calib-copy", action="store_true",
@@ -489,6 +528,15 @@ def main():
         return
     if args.small_blocks:
         small_blocks_only(args)
+        return
+    if args.plummer64k:
+        nb_cfg = {"metric": "Plummer N = 65536 block-step run to t = 1/8",
+                  "n_gpus": 1, "data": "synthetic",
+                  "config": {"workload": "plummer N=65536 eps=1/1024 seed=1002 eta=0.02 "
+                                         "dt_max=1/8, built-in launch shapes",
+                             "accumulation": args.mode}}
+        nb_cfg.update(plummer64k_run(args.mode))
+        print(json.dumps(nb_cfg), flush=True)
         return
 
     import numpy as np
@@ -658,31 +706,7 @@ def main():
             sorted_cost["n%d" % n_s] = row
         aux["smallest_first_sorted_cost"] = sorted_cost
 
-        # Plummer N=65536, eps=1/1024: full-N force-only throughput, then the
-        # block-step run to t=1/8 (wall time, steps, energy drift)
-        c2 = CONFIGS["plummer64k"]
-        p2, v2, m2 = (torch.from_numpy(a).cuda() for a in plummer(c2.n, c2.seed))
-        nb.force(p2, v2, m2, c2.eps2, None, args.mode)
-        torch.cuda.synchronize()
-        e0.record()
-        for _ in range(5):
-            nb.force(p2, v2, m2, c2.eps2, None, args.mode)
-        e1.record()
-        torch.cuda.synchronize()
-        aux["plummer64k_force_only_interactions_per_s"] = 5 * c2.n * (c2.n - 1.0) / (
-            e0.elapsed_time(e1) * 1e-3)
-        s2 = nb.System(p2, v2, m2, c2.eps2, eta=c2.eta, dt_max=c2.dt_max, mode=args.mode)
-        e_0 = s2.energy()
-        torch.cuda.synchronize()
-        ta = time.perf_counter()
-        steps2 = s2.run(c2.t_end)
-        torch.cuda.synchronize()
-        tb = time.perf_counter()
-        e_1 = s2.energy()
-        aux["plummer64k_run_seconds"] = tb - ta
-        aux["plummer64k_block_steps"] = steps2
-        aux["plummer64k_run_interactions_per_s"] = s2.interactions / (tb - ta)
-        aux["plummer64k_energy_drift_per_time_unit"] = abs((e_1 - e_0) / e_0) / c2.t_end
+        aux.update(plummer64k_run(args.mode))
 
         # batched ensemble: 256 clusters, N log-uniform in [256, 8192], to t = 1/16,
         # one persistent launch (inputs resident before timing; second run timed)

@@ -636,8 +636,13 @@ __global__ __launch_bounds__(64 * W) void force_jl_kernel(const KArgs a) {
 
 // Adds the S float64 partial sums of every output in a fixed order: the 64
 // lanes of a wave take 64 consecutive outputs, the RW waves of a workgroup
-// take contiguous quarters of the splits, and the wave sums are combined in
-// wave order through LDS.
+// take contiguous eighths of the splits, and the wave sums are combined in
+// wave order through LDS.  A lane issues its loads eight at a time and adds
+// them in split order, so a small block (few outputs, many splits) waits for
+// one memory latency per eight splits rather than per split.  At most four
+// workgroups per CU loop over the outputs: when the block size is counted on
+// the device the launch is sized for the largest block, and a grid that large
+// spends several microseconds dispatching groups that find nothing to do.
 __global__ __launch_bounds__(64 * RW) void reduce_parts_kernel(const KArgs a, int it, int waves) {
     __shared__ double red[RW][64];
     const int64_t n_i = block_size(a);
@@ -660,10 +665,26 @@ __global__ __launch_bounds__(64 * RW) void reduce_parts_kernel(const KArgs a, in
             const int64_t q = e / n_i, s = e - q * n_i;
             if (a.part_f32) {
                 const float *src = (const float *)a.part + q * n_i + s;
-                for (int64_t p = p0; p < p1; ++p) acc += (double)src[p * 7 * n_i];
+                int64_t p = p0;
+                for (; p + 8 <= p1; p += 8) {
+                    float v[8];
+#pragma unroll
+                    for (int u = 0; u < 8; ++u) v[u] = src[(p + u) * 7 * n_i];
+#pragma unroll
+                    for (int u = 0; u < 8; ++u) acc += (double)v[u];
+                }
+                for (; p < p1; ++p) acc += (double)src[p * 7 * n_i];
             } else {
                 const double *src = a.part + q * n_i + s;
-                for (int64_t p = p0; p < p1; ++p) acc += src[p * 7 * n_i];
+                int64_t p = p0;
+                for (; p + 8 <= p1; p += 8) {
+                    double v[8];
+#pragma unroll
+                    for (int u = 0; u < 8; ++u) v[u] = src[(p + u) * 7 * n_i];
+#pragma unroll
+                    for (int u = 0; u < 8; ++u) acc += v[u];
+                }
+                for (; p < p1; ++p) acc += src[p * 7 * n_i];
             }
         }
         red[wave][lane] = acc;
@@ -682,7 +703,7 @@ __global__ __launch_bounds__(64 * RW) void reduce_parts_kernel(const KArgs a, in
 
 int launch_reduce_parts(nbody_ctx *ctx, const KArgs &a, int it, int waves, int64_t n_i_max) {
     int64_t blocks = (7 * n_i_max + 63) / 64;
-    if (blocks > 16 * (int64_t)ctx->cus) blocks = 16 * (int64_t)ctx->cus;
+    if (blocks > 4 * (int64_t)ctx->cus) blocks = 4 * (int64_t)ctx->cus;
     if (blocks < 1) blocks = 1;
     hipLaunchKernelGGL(reduce_parts_kernel, dim3((unsigned)blocks), dim3(64 * RW), 0, ctx->stream,
                        a, it, waves);
