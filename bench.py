@@ -299,6 +299,33 @@ def small_block_sweep(P, V, M, eps2, cfg, reps=20):
     return small
 
 
+def valu_issue_bound(mix, kernel_ms):
+    """The pair kernel's VALU issue bound: the wave-instructions of each kind
+    its loop executes (the committed counter run of this launch) divided by
+    the issue rate of that kind measured now on this device
+    (nbody_valu_rates), summed, against this run's kernel time.  The
+    `rsq_coissued` figures leave the reciprocal square roots out of the sum,
+    as if the transcendental unit issued them beside the other instructions."""
+    import paper_cs_0702135_amd as nb
+    c = mix["counters_per_launch"]
+    count = {"v_fmac_f32": c["SQ_INSTS_VALU_FMA_F32"] + c["SQ_INSTS_VALU_ADD_F32"],
+             "v_mul_f32": c["SQ_INSTS_VALU_MUL_F32"],
+             "v_add_f64": c["SQ_INSTS_VALU_ADD_F64"],
+             "v_cvt_f32_f64": c["SQ_INSTS_VALU_CVT"],
+             "v_rsq_f32": c["SQ_INSTS_VALU_TRANS_F32"]}
+    rate = nb.valu_rates(8)
+    t_all = sum(count[k] / rate[k] for k in count)
+    t_co = t_all - count["v_rsq_f32"] / rate["v_rsq_f32"]
+    return {
+        "wave_instr_per_launch": {k: float("%.4g" % count[k]) for k in count},
+        "wave_instr_per_s": {k: float("%.4g" % rate[k]) for k in count},
+        "bound_ms": round(t_all * 1e3, 2),
+        "bound_ms_rsq_coissued": round(t_co * 1e3, 2),
+        "frac": round(t_all * 1e3 / kernel_ms, 4),
+        "frac_rsq_coissued": round(t_co * 1e3 / kernel_ms, 4),
+    }
+
+
 def plummer64k_run(mode):
     """Plummer N = 65536, eps = 1/1024, built-in launch shapes: the full-N
     force-only throughput, then the block-step run to t = 1/8 (wall time,
@@ -609,6 +636,7 @@ def main():
         roofline["executed_f32_flops_per_interaction"] = ex
         roofline["frac_executed"] = round(ex * inter_step / (k_ms * 1e-3) / 1e12
                                           / FP32_PEAK_TFLOPS, 4)
+        roofline["valu_issue"] = valu_issue_bound(mix, k_ms)
 
     out = {
         "metric": "pairwise acc+jerk interactions/s (Hermite block step, all N active)",

@@ -489,6 +489,23 @@ int nbody_tune_set(nbody_ctx *ctx, int64_t n_i_lo, int64_t n_i_hi,
 int nbody_profile(nbody_ctx *ctx, int enable, double *force_ms, double *reduce_ms,
                   int64_t *launches);
 
+/* ---- VALU issue rates (diagnostic, not an operation of the paper) --------
+ * For callers that state how close the float32-mode pair kernel (Eq. (1))
+ * runs to the hardware: its inner loop is made of five vector instruction
+ * kinds that do not issue at one rate.  For each kind a grid of
+ * waves_per_simd waves per SIMD on the context's device issues only that
+ * instruction (eight independent chains per lane, long unrolled runs), and
+ * rates[k] (HOST pointer, NBODY_VALU_KINDS doubles) receives the
+ * wave-instructions per second of the whole device (event-timed over three
+ * launches, at whatever clock the card holds under that load).  Kinds, in
+ * order: v_fmac_f32, v_mul_f32, v_add_f64, v_cvt_f32_f64, v_rsq_f32.  A
+ * loop's issue-bound time is the sum over kinds of its wave-instructions of
+ * that kind divided by the rate.  Uses the context's partial-sum buffer
+ * (grown if needed) and synchronises; about 50 ms.
+ *   waves_per_simd : 1..8, else NBODY_E_INVAL. */
+#define NBODY_VALU_KINDS 5
+int nbody_valu_rates(nbody_ctx *ctx, int waves_per_simd, double *rates);
+
 /* Remove every entry (back to the built-in default). */
 int nbody_tune_clear(nbody_ctx *ctx);
 /* The shape used for n_i (n_i < 0: the block-step shape); `out` is a HOST

@@ -553,6 +553,18 @@ def profile(enable=-1, device=None):
     return f.value, r.value, k.value
 
 
+VALU_KINDS = ("v_fmac_f32", "v_mul_f32", "v_add_f64", "v_cvt_f32_f64", "v_rsq_f32")
+
+
+def valu_rates(waves_per_simd=8, device=None):
+    """Issue rates of the VALU instruction kinds of the pair kernel's loop
+    (nbody_valu_rates): {kind: wave-instructions per second of the device}."""
+    ctx = context(device)
+    rates = (ctypes.c_double * L.NBODY_VALU_KINDS)()
+    ctx.check(ctx.lib.nbody_valu_rates(ctx.bind(), int(waves_per_simd), rates))
+    return dict(zip(VALU_KINDS, rates))
+
+
 class System:
     """Device-resident block-step integrator state (nbody_system)."""
 

@@ -24,6 +24,7 @@ NBODY_ACC_DS = 1
 NBODY_FIXED_DT = 2
 NBODY_ADJ_ACCUMULATE = 4
 NBODY_NOALLOC_MAX_NJ = 1048576
+NBODY_VALU_KINDS = 5
 
 P = ctypes.c_void_p
 I64 = ctypes.c_int64
@@ -103,6 +104,7 @@ SIGNATURES = {
     "nbody_profile": (INT, [P, INT, ctypes.POINTER(D), ctypes.POINTER(D),
                             ctypes.POINTER(I64)]),
     "nbody_tune_get": (INT, [P, I64, ctypes.POINTER(NBodyForceConfig)]),
+    "nbody_valu_rates": (INT, [P, INT, ctypes.POINTER(D)]),
 }
 
 _lib = None
