@@ -13,9 +13,10 @@
 //     square root; a wave sums `tile` consecutive j in float32, adds the
 //     tile sums of up to kFoldTiles tiles in float32 and that sum to a
 //     per-lane float64 total in LDS;
-//   * compensated mode: the pair arithmetic is float64 (gfx950 issues
-//     float64 FMAs at the rate of unpacked float32 ones), s^(-1/2) from the
-//     float32 estimate refined by one float64 Newton step, float64 sums;
+//   * compensated mode: the pair arithmetic is float64 (it issues at about
+//     half the float32 rate, but needs no float64-to-float32 conversions),
+//     s^(-1/2) from the float32 estimate refined by one float64 Newton step,
+//     float64 sums;
 //   * the W waves of a workgroup share the same i-particles and split their
 //     j range; their sums are combined in float64 through LDS in wave order;
 //   * the j range is also split across S workgroups when the active block
